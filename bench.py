@@ -1,0 +1,186 @@
+#!/usr/bin/env python3
+"""Throughput of the all-pairs DTW distance matrix on one MI355X.
+
+One step = one evaluation of the whole hot path on the workload's synthetic
+input, already resident in HBM: the staging kernel (padded FP32 copy of the
+series) and the DP kernels, i.e. one dtw_plan_execute.  The metric is giga
+cell updates per second over the admissible (in-window) cells of every pair.
+
+Printed: one JSON line with the value, the roofline of the dominant DP kernel
+(FP32 VALU bound, 3 VALU lane-operations per cell: sub, min3, fma), and the
+FP64 CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# MI355X: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz.  FP32 vector peak 157.3
+# TFLOP/s counts a packed FMA as 2 lanes x 2 flops; as VALU lane-operations
+# (one FMA, min3 or sub = 1 op) that is 78.64 T op/s with packed issue and
+# 39.32 T op/s with one unpacked VALU instruction per SIMD every 4 cycles.
+PEAK_LANE_OPS_T = 256 * 128 * 2.4e9 / 1e12          # 78.64
+PEAK_UNPACKED_LANE_OPS_T = 256 * 64 * 2.4e9 / 1e12  # 39.32
+OPS_PER_CELL = 3
+
+WORKLOADS = {
+    "c2": "equal-length banded matrix: 1000 random walks x 512, window 51",
+    "c5": "many short series: 8000 x 256, window 25",
+    "c3": "long series: 500 x 4096, no window",
+    "c1": "smallest: 20 x 64, no window",
+}
+
+
+def make_dataset(name):
+    from paper_2307_04904_amd import synth
+    return {"c1": synth.config1, "c2": synth.config2, "c3": synth.config3, "c5": synth.config5}[name]()
+
+
+def cpu_baseline(ds, gpu_out, target_s):
+    """Time the FP64 oracle on a seeded sample of pairs (all host cores) and check the GPU on them."""
+    import oracle
+    from paper_2307_04904_amd import synth
+    vals = synth.stored_as_f64(ds)
+    rng = np.random.default_rng(12345)
+    N = ds.N
+
+    def sample(k):
+        i = rng.integers(0, N, size=3 * k)
+        j = rng.integers(0, N, size=3 * k)
+        keep = i != j
+        return np.minimum(i, j)[keep][:k].astype(np.int32), np.maximum(i, j)[keep][:k].astype(np.int32)
+
+    def cells(pi, pj):
+        L = ds.lengths
+        if np.all(L == L[0]):
+            return oracle.band_cells(int(L[0]), int(L[0]), ds.window) * len(pi)
+        return sum(oracle.band_cells(int(L[a]), int(L[b]), ds.window) for a, b in zip(pi, pj))
+
+    pi, pj = sample(256)
+    t0 = time.perf_counter()
+    oracle.dtw_pairs(vals, ds.offsets, ds.lengths, pi, pj, ds.window)
+    t_cal = time.perf_counter() - t0
+    k = int(min(ds.n_pairs, max(256, 256 * target_s / max(t_cal, 1e-3))))
+    pi, pj = sample(k)
+    t0 = time.perf_counter()
+    ref, threads = oracle.dtw_pairs(vals, ds.offsets, ds.lengths, pi, pj, ds.window)
+    t = time.perf_counter() - t0
+    c = cells(pi, pj)
+    kk = pi.astype(np.int64) * N - pi.astype(np.int64) * (pi + 1) // 2 + (pj - pi - 1)
+    g = gpu_out[kk].astype(np.float64)
+    nz = ref > 0
+    rel = np.abs(g[nz] - ref[nz]) / ref[nz]
+    return {
+        "value": c / t / 1e9, "unit": "GCUPS", "cores": int(threads), "kind": "oracle",
+        "sample": "%d seeded random pairs of the same workload (%.3g admissible cells), FP64, %.1f s" % (len(pi), c, t),
+    }, {"pairs_checked": int(len(pi)), "max_rel_err": float(rel.max()) if rel.size else 0.0,
+        "mean_rel_err": float(rel.mean()) if rel.size else 0.0,
+        "zero_mismatch": int(np.count_nonzero(g[~nz] != 0.0))}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--kernel", default="auto", choices=["auto", "lane", "wave"])
+    ap.add_argument("--cpu-seconds", type=float, default=10.0, help="target duration of the CPU oracle sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args(argv)
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build measures one GPU only (the all-pairs matrix shards by pair ranges with no "
+              "exchange; see DESIGN.md). Run with --gpus 1.", file=sys.stderr)
+        return 2
+
+    import torch
+    from paper_2307_04904_amd import binding
+
+    ds = make_dataset(args.workload)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    series = binding.device_series(ds, dev)
+    out = torch.full((ds.n_pairs,), float("nan"), dtype=torch.float32, device=dev)
+    plan = binding.Plan([(series, ds.lengths, ds.offsets, ds.window, out)], dtype=ds.dtype,
+                        kernel=args.kernel, timing=True)
+    info = plan.info()
+    stream = torch.cuda.current_stream(dev)
+
+    for _ in range(args.warmup):
+        plan.execute(stream)
+    torch.cuda.synchronize(dev)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        plan.execute(stream)
+    ev1.record(stream)
+    torch.cuda.synchronize(dev)
+    wall = time.perf_counter() - t0
+    ms_per_step = ev0.elapsed_time(ev1) / args.steps
+
+    # DP-kernel-only durations (HIP events recorded by the library on the same stream)
+    kms = []
+    for _ in range(max(3, min(args.steps, 20))):
+        plan.execute(stream)
+        kms.append(plan.last_kernel_ms())
+    k_avg = statistics.mean(kms)
+
+    cells = info["band_cells"]
+    value = cells / (ms_per_step * 1e-3) / 1e9
+    achieved = OPS_PER_CELL * cells / (k_avg * 1e-3) / 1e12
+    line = {
+        "metric": "DTW cell updates/s (GCUPS) for all-pairs matrix; % of FP32 VALU peak",
+        "value": round(value, 2),
+        "unit": "GCUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": ds.name, "description": WORKLOADS[args.workload], "N": ds.N,
+                   "length": int(ds.lengths.max()), "window": ds.window, "pairs": info["pairs"],
+                   "band_cells": cells, "swept_cells": info["computed_cells"], "kernel": args.kernel},
+        "pct_peak_cell_rate": round(100.0 * value / (PEAK_LANE_OPS_T * 1e3 / OPS_PER_CELL), 2),
+        "roofline": {
+            "bound": "alu",
+            "achieved": round(achieved, 3),
+            "peak": round(PEAK_LANE_OPS_T, 2),
+            "unit": "TOP/s (FP32 VALU lane-ops)",
+            "frac": round(achieved / PEAK_LANE_OPS_T, 4),
+            "frac_of_unpacked_issue": round(achieved / PEAK_UNPACKED_LANE_OPS_T, 4),
+            "kernel_ms": round(k_avg, 4),
+            "ops_per_launch": OPS_PER_CELL * cells,
+            "traffic": None,
+        },
+        "wall_s": round(wall, 3),
+    }
+    if not args.no_cpu_baseline:
+        torch.cuda.synchronize(dev)
+        gpu_out = out.cpu().numpy()
+        base, check = cpu_baseline(ds, gpu_out, args.cpu_seconds)
+        line["cpu_baseline"] = base
+        line["gpu_vs_oracle_on_sample"] = check
+    plan.destroy()
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

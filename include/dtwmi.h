@@ -1,0 +1,149 @@
+/*
+ * dtwmi.h -- C ABI of the MI355X (gfx950) all-pairs dynamic time warping library.
+ *
+ * What is computed (paper "Fast dynamic time warping and clustering in C++",
+ * section "Mathematical background"):
+ *   - for two series x (length n) and y (length m), the cumulative cost of
+ *     Eq. (c):  c(i,j) = (x_i - y_j)^2 + min{c(i-1,j-1), c(i-1,j), c(i,j-1)},
+ *     c(0,0) = 0, c(i,0) = c(0,j) = +inf (1-based), result c(n,m).  No square
+ *     root is taken.
+ *   - a warping window w (paper, Introduction: a window of 99 lets the first
+ *     point reach at most the hundredth point of the other series): cell
+ *     (i,j) is admissible iff |i-j| <= max(w, |n-m|); w < 0 means no window.
+ *     Inadmissible cells are +inf.
+ *   - the symmetric distance matrix D with d(i,j) = cost of the pair (i,j)
+ *     (same section, figure "c_to_d"), stored as its condensed upper
+ *     triangle: entry k(i,j) = i*N - i*(i+1)/2 + (j-i-1) for 0 <= i < j < N,
+ *     row-major, N*(N-1)/2 floats.  The zero diagonal is not stored.
+ *
+ * Conventions common to every entry point:
+ *   - Every function returns a dtw_status.  Nothing aborts, throws or prints.
+ *     On failure dtw_last_error() returns a message for the calling thread.
+ *   - "device" pointers are HIP device memory (hipMalloc or a torch tensor on
+ *     the GPU); "host" pointers are ordinary CPU memory.  The caller owns every
+ *     buffer it passes in.
+ *   - All arguments are validated on the host before any HIP call.
+ *   - Series values must be finite; results for NaN or inf inputs are
+ *     unspecified.  The output is always FP32.
+ *   - Series may have any length >= 1; the wavefront kernel covers the
+ *     shorter series of a pair up to 4096 points, a longer shorter-series
+ *     returns DTW_ERR_UNSUPPORTED.
+ */
+#ifndef DTWMI_H
+#define DTWMI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    DTW_OK = 0,
+    DTW_ERR_INVALID_ARG = 1,   /* bad pointer, count, length, enum value */
+    DTW_ERR_UNSUPPORTED = 2,   /* valid request outside what the kernels cover */
+    DTW_ERR_OUT_OF_MEMORY = 3, /* device or host allocation failed */
+    DTW_ERR_HIP = 4            /* a HIP runtime call or kernel launch failed */
+} dtw_status;
+
+/* Storage type of the input series (all accumulate in FP32 or FP64). */
+typedef enum { DTW_F32 = 0, DTW_BF16 = 1, DTW_F16 = 2 } dtw_dtype;
+
+/* Accumulation of the cumulative cost:
+ *   PLAIN: FP32 sub, min, fused multiply-add per cell.
+ *   KAHAN: FP32 with a compensation term carried per cell and a compensated
+ *          add of every local cost (the min compares the running sums).
+ *   FP64:  the whole recurrence in FP64, the final cost rounded once to FP32. */
+typedef enum { DTW_ACC_PLAIN = 0, DTW_ACC_KAHAN = 1, DTW_ACC_FP64 = 2 } dtw_accum;
+
+/* Kernel family; AUTO picks per dataset.  The others exist for tests/benches.
+ *   LANE: one pair per lane, the band row kept in registers (all series of the
+ *         dataset of equal length, 2*w+1 <= 127, PLAIN only).
+ *   WAVE: one pair per 64-lane wavefront sweeping anti-diagonals, each lane
+ *         owning a strip of rows (any lengths, any window, any accumulation). */
+typedef enum { DTW_KERNEL_AUTO = 0, DTW_KERNEL_LANE = 1, DTW_KERNEL_WAVE = 2 } dtw_kernel;
+
+/* One dataset: N series concatenated in one device buffer. */
+typedef struct dtw_dataset {
+    const void *series;     /* device: values of all series, element type given by dtw_options.dtype */
+    const int32_t *lengths; /* host: N lengths, each >= 1 */
+    const int64_t *offsets; /* host: N element offsets of each series inside `series`, >= 0 */
+    int32_t N;              /* number of series, >= 0; N < 2 writes nothing */
+    int32_t window;         /* Sakoe-Chiba window w; < 0 = no window */
+    float *out_condensed;   /* device: N*(N-1)/2 floats, written in condensed order */
+} dtw_dataset;
+
+typedef struct dtw_options {
+    int32_t dtype;  /* dtw_dtype */
+    int32_t accum;  /* dtw_accum */
+    int32_t kernel; /* dtw_kernel (0 = AUTO) */
+    int32_t flags;  /* bit 0: record HIP events around the DP kernels (plan API only) */
+    void *stream;   /* hipStream_t used by dtw_pairwise_ex; NULL = default stream */
+} dtw_options;
+
+#define DTW_FLAG_TIMING 1
+
+typedef struct dtw_plan_s *dtw_plan;
+
+/* Statistics of a plan (host values, filled by dtw_plan_info). */
+typedef struct dtw_plan_stats {
+    int64_t pairs;           /* number of pairs (condensed entries) written per execute */
+    int64_t band_cells;      /* admissible DP cells summed over all pairs */
+    int64_t computed_cells;  /* cells the kernels sweep, padding included */
+    int64_t workspace_bytes; /* device memory owned by the plan */
+    int32_t n_launches;      /* kernel launches per execute, staging included */
+    int32_t n_lane_items;    /* LANE work items (64 pairs each) */
+    int64_t n_wave_items;    /* WAVE work items (one pair each) */
+} dtw_plan_stats;
+
+/*
+ * Short form: FP32 input, PLAIN accumulation, default stream, automatic kernel.
+ * series: device; lengths, offsets: host; out_condensed: device.
+ * Blocks until the result is written (it builds and frees a plan internally).
+ */
+int dtw_pairwise(const float *series, const int32_t *lengths, const int64_t *offsets,
+                 int32_t N, int32_t window, float *out_condensed);
+
+/* One dataset with explicit options; blocks until the result is written. */
+int dtw_pairwise_ex(const dtw_dataset *ds, const dtw_options *opt);
+
+/*
+ * Plans: validate, enumerate and tile all pairs of n_datasets datasets once,
+ * allocate the device workspace and upload the tile lists.  The plan keeps
+ * the dataset device pointers (series, out_condensed) and the caller keeps
+ * them alive, with unchanged lengths, until dtw_plan_destroy.  Host arrays
+ * are copied and may be freed after dtw_plan_create returns.
+ */
+int dtw_plan_create(dtw_plan *plan, const dtw_dataset *ds, int32_t n_datasets,
+                    const dtw_options *opt);
+
+/*
+ * Enqueue one full evaluation (staging of the inputs into the padded FP32
+ * workspace, then every DP kernel) on `stream` (hipStream_t, NULL = default).
+ * Allocates nothing and never synchronises, so it may be captured into a HIP
+ * graph.  Results are valid after the stream is synchronised.  Executions of
+ * one plan on different streams must not overlap (they share the workspace).
+ */
+int dtw_plan_execute(dtw_plan plan, void *stream);
+
+/* Milliseconds spent in the DP kernels by the last execute (DTW_FLAG_TIMING plans only); synchronises on the end event. */
+int dtw_plan_last_kernel_ms(dtw_plan plan, float *ms);
+
+int dtw_plan_info(dtw_plan plan, dtw_plan_stats *stats);
+
+int dtw_plan_destroy(dtw_plan plan);
+
+/* Admissible cells of one n x m problem under window w (host arithmetic only). */
+int dtw_band_cells(int32_t n, int32_t m, int32_t window, int64_t *cells);
+
+/* Message describing the last failure on the calling thread ("" if none). */
+const char *dtw_last_error(void);
+
+/* Library version, major*10000 + minor*100 + patch. */
+int32_t dtw_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DTWMI_H */

@@ -1,0 +1,220 @@
+"""Thin ctypes binding of libdtwmi.so (declared in include/dtwmi.h).
+
+Argument marshalling only: device buffers are torch tensors on the GPU (their
+``data_ptr()`` is passed through), host arrays are numpy arrays, streams are
+torch streams.  Every computation happens in the HIP kernels behind the C ABI;
+if the library is missing this module raises instead of computing anything.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_build", "libdtwmi.so")
+
+DTW_OK, DTW_ERR_INVALID_ARG, DTW_ERR_UNSUPPORTED, DTW_ERR_OUT_OF_MEMORY, DTW_ERR_HIP = range(5)
+DTYPES = {"f32": 0, "bf16": 1, "f16": 2}
+ACCUM = {"plain": 0, "kahan": 1, "fp64": 2}
+KERNELS = {"auto": 0, "lane": 1, "wave": 2}
+DTW_FLAG_TIMING = 1
+
+EXPORTED = ["dtw_pairwise", "dtw_pairwise_ex", "dtw_plan_create", "dtw_plan_execute",
+            "dtw_plan_last_kernel_ms", "dtw_plan_info", "dtw_plan_destroy", "dtw_band_cells",
+            "dtw_last_error", "dtw_version"]
+
+
+class DtwError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("dtwmi error %d: %s" % (code, msg))
+        self.code = code
+
+
+class dtw_dataset(ctypes.Structure):
+    _fields_ = [("series", ctypes.c_void_p), ("lengths", ctypes.POINTER(ctypes.c_int32)),
+                ("offsets", ctypes.POINTER(ctypes.c_int64)), ("N", ctypes.c_int32),
+                ("window", ctypes.c_int32), ("out_condensed", ctypes.c_void_p)]
+
+
+class dtw_options(ctypes.Structure):
+    _fields_ = [("dtype", ctypes.c_int32), ("accum", ctypes.c_int32), ("kernel", ctypes.c_int32),
+                ("flags", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+
+
+class dtw_plan_stats(ctypes.Structure):
+    _fields_ = [("pairs", ctypes.c_int64), ("band_cells", ctypes.c_int64), ("computed_cells", ctypes.c_int64),
+                ("workspace_bytes", ctypes.c_int64), ("n_launches", ctypes.c_int32),
+                ("n_lane_items", ctypes.c_int32), ("n_wave_items", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libdtwmi.so (raises DtwError if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise DtwError(-1, "%s is missing: build it with __graft_entry__.build()" % path)
+    lib = ctypes.CDLL(path)
+    P = ctypes.POINTER
+    i32p, i64p = P(ctypes.c_int32), P(ctypes.c_int64)
+    lib.dtw_pairwise.argtypes = [ctypes.c_void_p, i32p, i64p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p]
+    lib.dtw_pairwise_ex.argtypes = [P(dtw_dataset), P(dtw_options)]
+    lib.dtw_plan_create.argtypes = [P(ctypes.c_void_p), P(dtw_dataset), ctypes.c_int32, P(dtw_options)]
+    lib.dtw_plan_execute.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+    lib.dtw_plan_last_kernel_ms.argtypes = [ctypes.c_void_p, P(ctypes.c_float)]
+    lib.dtw_plan_info.argtypes = [ctypes.c_void_p, P(dtw_plan_stats)]
+    lib.dtw_plan_destroy.argtypes = [ctypes.c_void_p]
+    lib.dtw_band_cells.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, i64p]
+    lib.dtw_last_error.argtypes = []
+    lib.dtw_last_error.restype = ctypes.c_char_p
+    lib.dtw_version.argtypes = []
+    lib.dtw_version.restype = ctypes.c_int32
+    for name in EXPORTED:
+        if name not in ("dtw_last_error", "dtw_version"):
+            getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(rc):
+    if rc != DTW_OK:
+        raise DtwError(rc, dtw_last_error())
+
+
+def dtw_last_error() -> str:
+    return load().dtw_last_error().decode()
+
+
+def dtw_version() -> int:
+    return int(load().dtw_version())
+
+
+def dtw_band_cells(n: int, m: int, window: int) -> int:
+    out = ctypes.c_int64()
+    _check(load().dtw_band_cells(int(n), int(m), int(window), ctypes.byref(out)))
+    return int(out.value)
+
+
+def _host_arrays(lengths, offsets):
+    ln = np.ascontiguousarray(lengths, dtype=np.int32)
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    return ln, off
+
+
+def _stream_handle(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _make_dataset(series, lengths, offsets, window, out):
+    ln, off = _host_arrays(lengths, offsets)
+    d = dtw_dataset()
+    d.series = ctypes.c_void_p(series.data_ptr() if series is not None else 0)
+    d.lengths = ln.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    d.offsets = off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    d.N = len(ln)
+    d.window = int(window)
+    d.out_condensed = ctypes.c_void_p(out.data_ptr() if out is not None else 0)
+    return d, (ln, off)
+
+
+def _options(dtype="f32", accum="plain", kernel="auto", flags=0, stream=None):
+    o = dtw_options()
+    o.dtype = DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
+    o.accum = ACCUM[accum] if isinstance(accum, str) else int(accum)
+    o.kernel = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
+    o.flags = int(flags)
+    o.stream = _stream_handle(stream) if stream is not False else ctypes.c_void_p(0)
+    return o
+
+
+def dtw_pairwise(series, lengths, offsets, N, window, out_condensed):
+    """Short form of the C ABI: FP32 device series, condensed FP32 device output (blocking)."""
+    ln, off = _host_arrays(lengths, offsets)
+    _check(load().dtw_pairwise(ctypes.c_void_p(series.data_ptr()), ln.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                               off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), int(N), int(window),
+                               ctypes.c_void_p(out_condensed.data_ptr())))
+
+
+def dtw_pairwise_ex(series, lengths, offsets, window, out_condensed, dtype="f32", accum="plain", kernel="auto",
+                    stream=None):
+    """One dataset with options (blocking).  `series` holds f32, bf16 (as int16/uint16 bits) or f16 values."""
+    d, keep = _make_dataset(series, lengths, offsets, window, out_condensed)
+    o = _options(dtype, accum, kernel, 0, stream)
+    _check(load().dtw_pairwise_ex(ctypes.byref(d), ctypes.byref(o)))
+    del keep
+
+
+class Plan:
+    """dtw_plan_create / execute / destroy for one or more datasets.
+
+    datasets: list of (series_tensor, lengths, offsets, window, out_tensor).
+    The tensors must stay alive, at the same address, while the plan exists.
+    """
+
+    def __init__(self, datasets, dtype="f32", accum="plain", kernel="auto", timing=False):
+        self._lib = load()
+        arr = (dtw_dataset * max(1, len(datasets)))()
+        self._keep = []
+        for k, (series, lengths, offsets, window, out) in enumerate(datasets):
+            d, keep = _make_dataset(series, lengths, offsets, window, out)
+            arr[k] = d
+            self._keep.append((keep, series, out))
+        o = _options(dtype, accum, kernel, DTW_FLAG_TIMING if timing else 0, False)
+        self._h = ctypes.c_void_p()
+        _check(self._lib.dtw_plan_create(ctypes.byref(self._h), arr, len(datasets), ctypes.byref(o)))
+
+    def execute(self, stream=None):
+        _check(self._lib.dtw_plan_execute(self._h, _stream_handle(stream)))
+
+    def last_kernel_ms(self) -> float:
+        ms = ctypes.c_float()
+        _check(self._lib.dtw_plan_last_kernel_ms(self._h, ctypes.byref(ms)))
+        return float(ms.value)
+
+    def info(self) -> dict:
+        st = dtw_plan_stats()
+        _check(self._lib.dtw_plan_info(self._h, ctypes.byref(st)))
+        return {name: int(getattr(st, name)) for name, _ in dtw_plan_stats._fields_}
+
+    def destroy(self):
+        if self._h:
+            _check(self._lib.dtw_plan_destroy(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def device_series(ds, device="cuda"):
+    """Upload a synth.Dataset's stored values as a torch tensor (bf16 kept as raw 16-bit words)."""
+    import torch
+    v = ds.values
+    if ds.dtype == "bf16":
+        t = torch.from_numpy(v.view(np.int16).copy())
+    elif ds.dtype == "f16":
+        t = torch.from_numpy(v.copy())
+    else:
+        t = torch.from_numpy(np.ascontiguousarray(v, dtype=np.float32))
+    return t.to(device)
+
+
+def pairwise(ds, accum="plain", kernel="auto", device="cuda", out=None):
+    """Condensed DTW matrix of a synth.Dataset on the GPU, returned as a torch tensor (blocking)."""
+    import torch
+    series = device_series(ds, device)
+    if out is None:
+        out = torch.full((max(0, ds.n_pairs),), float("nan"), dtype=torch.float32, device=device)
+    dtw_pairwise_ex(series, ds.lengths, ds.offsets, ds.window, out, dtype=ds.dtype, accum=accum, kernel=kernel)
+    return out

@@ -1,0 +1,420 @@
+// Host side of the C ABI: validation, pair enumeration and tiling, workspace
+// layout, plan execution.  See include/dtwmi.h for the contract.
+//
+// Pair enumeration.  The paper computes all p(p-1)/2 pairwise distances
+// ("Mathematical background") and fills the symmetric matrix D.  This library
+// writes each unordered pair once into the condensed upper triangle.
+//  * lane-band datasets (all series of equal length, narrow band, PLAIN):
+//    series a is paired with the series at cyclic distances 1..h_a
+//    ((a+d) mod N), h_a = floor((N-1)/2), plus the pair at distance N/2 for
+//    a < N/2 when N is even.  Every unordered pair appears exactly once and
+//    every series gets the same number of partners, so the 64-pair work items
+//    are almost all full.
+//  * wavefront datasets: one item per pair (i<j); the shorter series is the
+//    one spread over the lanes.  Items are grouped by kernel instance and each
+//    group is sorted by decreasing cell count, so the longest pairs start first.
+#include "dtw_internal.h"
+#include "dtwmi.h"
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <tuple>
+#include <vector>
+
+using namespace dtwmi;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+    return fail(DTW_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Admissible cells of an n x m problem with band b (b < 0: none).  Closed
+// form of sum_i |{j : |i-j| <= b, 0 <= j < m}|, valid because b >= |n-m|.
+int64_t band_cells(int64_t n, int64_t m, int64_t b) {
+    if (n <= 0 || m <= 0) return 0;
+    if (b < 0 || b >= std::max(n, m) - 1) return n * m;
+    // sum over i of (min(m-1, i+b) + 1) - max(0, i-b)
+    int64_t upper = 0;
+    const int64_t i_split = std::min(n - 1, m - b - 1);  // rows with i+b+1 <= m
+    if (i_split >= 0) upper += (i_split + 1) * (b + 1) + i_split * (i_split + 1) / 2;
+    const int64_t rest = (n - 1) - std::max<int64_t>(i_split, -1);
+    upper += rest * m;
+    int64_t lower = 0;
+    if (n - 1 > b) {
+        const int64_t t = n - 1 - b;
+        lower = t * (t + 1) / 2;
+    }
+    return upper - lower;
+}
+
+int64_t effective_band(int32_t w, int32_t n, int32_t m) {
+    if (w < 0) return -1;
+    const int64_t d = n > m ? (int64_t)n - m : (int64_t)m - n;
+    const int64_t b = std::max<int64_t>(w, d);
+    return b >= std::max(n, m) - 1 ? -1 : b;
+}
+
+struct LaneGroup {
+    int W;
+    int64_t begin, count;
+};
+
+struct WaveGroup {
+    int H;
+    bool banded;
+    int64_t begin, count;
+};
+
+}  // namespace
+
+struct dtw_plan_s {
+    int device = 0;
+    int dtype = 0, accum = 0, kernel = 0, flags = 0;
+    int32_t nseries = 0;
+    void *dev_block = nullptr;  // one allocation holding everything below
+    size_t dev_bytes = 0;
+    float *ws = nullptr;
+    SeriesSrc *d_src = nullptr;
+    SeriesInfo *d_ser = nullptr;
+    DatasetInfo *d_ds = nullptr;
+    LaneItem *d_lane = nullptr;
+    WaveItem *d_wave = nullptr;
+    std::vector<LaneGroup> lane_groups;
+    std::vector<WaveGroup> wave_groups;
+    dtw_plan_stats stats{};
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    bool timed_once = false;
+};
+
+namespace {
+
+int validate_options(const dtw_options *opt) {
+    if (!opt) return DTW_OK;
+    if (opt->dtype < DTW_F32 || opt->dtype > DTW_F16) return fail(DTW_ERR_INVALID_ARG, "unknown dtype %d", opt->dtype);
+    if (opt->accum < DTW_ACC_PLAIN || opt->accum > DTW_ACC_FP64)
+        return fail(DTW_ERR_INVALID_ARG, "unknown accumulation mode %d", opt->accum);
+    if (opt->kernel < DTW_KERNEL_AUTO || opt->kernel > DTW_KERNEL_WAVE)
+        return fail(DTW_ERR_INVALID_ARG, "unknown kernel family %d", opt->kernel);
+    if (opt->flags & ~DTW_FLAG_TIMING) return fail(DTW_ERR_INVALID_ARG, "unknown flags 0x%x", opt->flags);
+    return DTW_OK;
+}
+
+int validate_dataset(const dtw_dataset &d, int idx) {
+    if (d.N < 0) return fail(DTW_ERR_INVALID_ARG, "dataset %d: N=%d < 0", idx, d.N);
+    if (d.N < 2) return DTW_OK;
+    if (!d.series) return fail(DTW_ERR_INVALID_ARG, "dataset %d: series is NULL", idx);
+    if (!d.out_condensed) return fail(DTW_ERR_INVALID_ARG, "dataset %d: out_condensed is NULL", idx);
+    if (!d.lengths || !d.offsets) return fail(DTW_ERR_INVALID_ARG, "dataset %d: lengths/offsets is NULL", idx);
+    for (int32_t s = 0; s < d.N; ++s) {
+        if (d.lengths[s] < 1) return fail(DTW_ERR_INVALID_ARG, "dataset %d: lengths[%d]=%d < 1", idx, s, d.lengths[s]);
+        if (d.offsets[s] < 0) return fail(DTW_ERR_INVALID_ARG, "dataset %d: offsets[%d] < 0", idx, s);
+    }
+    return DTW_OK;
+}
+
+void destroy_plan(dtw_plan p) {
+    if (!p) return;
+    if (p->dev_block) (void)hipFree(p->dev_block);
+    if (p->ev0) (void)hipEventDestroy(p->ev0);
+    if (p->ev1) (void)hipEventDestroy(p->ev1);
+    delete p;
+}
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+}  // namespace
+
+extern "C" {
+
+const char *dtw_last_error(void) { return g_err.c_str(); }
+
+int32_t dtw_version(void) { return 100; }
+
+int dtw_band_cells(int32_t n, int32_t m, int32_t window, int64_t *cells) {
+    if (!cells) return fail(DTW_ERR_INVALID_ARG, "cells is NULL");
+    if (n < 0 || m < 0) return fail(DTW_ERR_INVALID_ARG, "negative length");
+    *cells = band_cells(n, m, effective_band(window, n, m));
+    return DTW_OK;
+}
+
+int dtw_plan_create(dtw_plan *plan_out, const dtw_dataset *ds, int32_t n_datasets, const dtw_options *opt) {
+    g_err.clear();
+    if (!plan_out) return fail(DTW_ERR_INVALID_ARG, "plan is NULL");
+    *plan_out = nullptr;
+    if (n_datasets < 0) return fail(DTW_ERR_INVALID_ARG, "n_datasets=%d < 0", n_datasets);
+    if (n_datasets > 0 && !ds) return fail(DTW_ERR_INVALID_ARG, "datasets is NULL");
+    int rc = validate_options(opt);
+    if (rc) return rc;
+    for (int32_t d = 0; d < n_datasets; ++d)
+        if ((rc = validate_dataset(ds[d], d))) return rc;
+
+    const int dtype = opt ? opt->dtype : DTW_F32;
+    const int accum = opt ? opt->accum : DTW_ACC_PLAIN;
+    const int kernel = opt ? opt->kernel : DTW_KERNEL_AUTO;
+    const int flags = opt ? opt->flags : 0;
+
+    // ---- host-side planning (no HIP calls) ----
+    std::vector<SeriesSrc> src;
+    std::vector<SeriesInfo> ser;
+    std::vector<DatasetInfo> dsi;
+    std::vector<LaneItem> lane_items;
+    std::map<int, std::vector<LaneItem>> lane_by_w;
+    std::map<std::pair<int, bool>, std::vector<std::pair<int64_t, WaveItem>>> wave_by_kind;
+    dtw_plan_stats st{};
+    size_t ws_floats = 0;
+    const size_t elem = dtype == DTW_F32 ? 4 : 2;
+
+    for (int32_t d = 0; d < n_datasets; ++d) {
+        const dtw_dataset &D = ds[d];
+        DatasetInfo info{};
+        info.out = D.out_condensed;
+        info.N = D.N;
+        info.window = D.window;
+        info.series_base = static_cast<int32_t>(ser.size());
+        if (D.N < 2) {
+            info.L = -1;
+            dsi.push_back(info);
+            continue;
+        }
+        bool uniform = true;
+        for (int32_t s = 0; s < D.N; ++s) {
+            uniform = uniform && D.lengths[s] == D.lengths[0];
+            SeriesSrc ss{D.series, D.offsets[s], D.lengths[s], dtype};
+            SeriesInfo si{};
+            si.len = D.lengths[s];
+            si.pstart = static_cast<int64_t>(ws_floats) + kPad;
+            ws_floats += align_up(static_cast<size_t>(D.lengths[s]) + 2 * kPad, 4);
+            src.push_back(ss);
+            ser.push_back(si);
+        }
+        (void)elem;
+        info.L = uniform ? D.lengths[0] : -1;
+        dsi.push_back(info);
+        const int64_t npairs = (int64_t)D.N * (D.N - 1) / 2;
+        st.pairs += npairs;
+
+        // Kernel family for this dataset.
+        int lane_w = 0;
+        if (uniform && accum == DTW_ACC_PLAIN) {
+            const int32_t L = D.lengths[0];
+            const int32_t b = (D.window < 0 || D.window >= L - 1) ? L - 1 : D.window;
+            if (lane_width_supported(2 * b + 1)) lane_w = 2 * b + 1;
+        }
+        if (kernel == DTW_KERNEL_LANE && !lane_w)
+            return fail(DTW_ERR_UNSUPPORTED,
+                        "dataset %d: the lane-band kernel needs equal lengths, PLAIN accumulation and 2*w+1 <= %d",
+                        d, kLaneMaxW);
+        if (kernel == DTW_KERNEL_WAVE) lane_w = 0;
+
+        if (lane_w) {
+            const int32_t N = D.N, L = D.lengths[0], b = (lane_w - 1) / 2;
+            st.band_cells += npairs * band_cells(L, L, b >= L - 1 ? -1 : b);
+            for (int32_t a = 0; a < N; ++a) {
+                int32_t h = (N - 1) / 2;
+                if (N % 2 == 0 && a < N / 2) h = N / 2;
+                for (int32_t d0 = 1; d0 <= h; d0 += 64) {
+                    const int32_t cnt = std::min(64, h - d0 + 1);
+                    lane_by_w[lane_w].push_back(LaneItem{d, a, d0, cnt});
+                    st.computed_cells += (int64_t)64 * L * lane_w;
+                }
+            }
+        } else {
+            for (int32_t i = 0; i < D.N; ++i) {
+                for (int32_t j = i + 1; j < D.N; ++j) {
+                    const int32_t ni = D.lengths[i], nj = D.lengths[j];
+                    const bool swap = nj < ni;
+                    const int32_t rows = swap ? j : i, cols = swap ? i : j;
+                    const int32_t n = std::min(ni, nj), m = std::max(ni, nj);
+                    const int H = wave_rows_per_lane(n);
+                    if (!H)
+                        return fail(DTW_ERR_UNSUPPORTED,
+                                    "dataset %d: pair (%d,%d) has both series longer than %d points", d, i, j,
+                                    kWaveMaxRows);
+                    const int64_t b = effective_band(D.window, n, m);
+                    const int64_t cells = band_cells(n, m, b);
+                    st.band_cells += cells;
+                    st.computed_cells += (int64_t)64 * H * (m + (n - 1) / H);
+                    wave_by_kind[{H, b >= 0}].push_back({cells, WaveItem{d, rows, cols, (int32_t)b}});
+                }
+            }
+        }
+    }
+
+    dtw_plan p = new (std::nothrow) dtw_plan_s;
+    if (!p) return fail(DTW_ERR_OUT_OF_MEMORY, "host allocation failed");
+    p->dtype = dtype;
+    p->accum = accum;
+    p->kernel = kernel;
+    p->flags = flags;
+    p->nseries = static_cast<int32_t>(ser.size());
+
+    std::vector<WaveItem> wave_items;
+    for (auto &kv : lane_by_w) {
+        p->lane_groups.push_back(LaneGroup{kv.first, (int64_t)lane_items.size(), (int64_t)kv.second.size()});
+        lane_items.insert(lane_items.end(), kv.second.begin(), kv.second.end());
+    }
+    // Larger strips first; inside a group, larger pairs first.
+    for (auto it = wave_by_kind.rbegin(); it != wave_by_kind.rend(); ++it) {
+        auto &v = it->second;
+        std::stable_sort(v.begin(), v.end(), [](const std::pair<int64_t, WaveItem> &a,
+                                                const std::pair<int64_t, WaveItem> &b) { return a.first > b.first; });
+        p->wave_groups.push_back(WaveGroup{it->first.first, it->first.second, (int64_t)wave_items.size(),
+                                           (int64_t)v.size()});
+        for (auto &e : v) wave_items.push_back(e.second);
+    }
+    st.n_lane_items = static_cast<int32_t>(lane_items.size());
+    st.n_wave_items = static_cast<int64_t>(wave_items.size());
+    st.n_launches = (p->nseries > 0 ? 1 : 0) + (int32_t)p->lane_groups.size() + (int32_t)p->wave_groups.size();
+
+    // ---- device allocation and upload ----
+    ws_floats += 256;  // slack past the last slot
+    size_t off = 0;
+    const size_t o_ws = off;
+    off = align_up(off + ws_floats * sizeof(float), 256);
+    const size_t o_src = off;
+    off = align_up(off + src.size() * sizeof(SeriesSrc), 256);
+    const size_t o_ser = off;
+    off = align_up(off + ser.size() * sizeof(SeriesInfo), 256);
+    const size_t o_ds = off;
+    off = align_up(off + dsi.size() * sizeof(DatasetInfo), 256);
+    const size_t o_lane = off;
+    off = align_up(off + lane_items.size() * sizeof(LaneItem), 256);
+    const size_t o_wave = off;
+    off = align_up(off + wave_items.size() * sizeof(WaveItem), 256);
+    p->dev_bytes = off;
+    st.workspace_bytes = static_cast<int64_t>(off);
+    p->stats = st;
+
+    hipError_t e = hipGetDevice(&p->device);
+    if (e != hipSuccess) {
+        destroy_plan(p);
+        return hip_fail(e, "hipGetDevice");
+    }
+    e = hipMalloc(&p->dev_block, p->dev_bytes);
+    if (e != hipSuccess) {
+        destroy_plan(p);
+        return fail(DTW_ERR_OUT_OF_MEMORY, "hipMalloc(%zu bytes): %s", p->dev_bytes, hipGetErrorString(e));
+    }
+    char *base = static_cast<char *>(p->dev_block);
+    p->ws = reinterpret_cast<float *>(base + o_ws);
+    p->d_src = reinterpret_cast<SeriesSrc *>(base + o_src);
+    p->d_ser = reinterpret_cast<SeriesInfo *>(base + o_ser);
+    p->d_ds = reinterpret_cast<DatasetInfo *>(base + o_ds);
+    p->d_lane = reinterpret_cast<LaneItem *>(base + o_lane);
+    p->d_wave = reinterpret_cast<WaveItem *>(base + o_wave);
+    struct Up {
+        void *dst;
+        const void *src;
+        size_t bytes;
+    } ups[] = {{p->d_src, src.data(), src.size() * sizeof(SeriesSrc)},
+               {p->d_ser, ser.data(), ser.size() * sizeof(SeriesInfo)},
+               {p->d_ds, dsi.data(), dsi.size() * sizeof(DatasetInfo)},
+               {p->d_lane, lane_items.data(), lane_items.size() * sizeof(LaneItem)},
+               {p->d_wave, wave_items.data(), wave_items.size() * sizeof(WaveItem)}};
+    for (const Up &u : ups) {
+        if (!u.bytes) continue;
+        e = hipMemcpy(u.dst, u.src, u.bytes, hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            destroy_plan(p);
+            return hip_fail(e, "hipMemcpy (plan upload)");
+        }
+    }
+    if (flags & DTW_FLAG_TIMING) {
+        if ((e = hipEventCreate(&p->ev0)) != hipSuccess || (e = hipEventCreate(&p->ev1)) != hipSuccess) {
+            destroy_plan(p);
+            return hip_fail(e, "hipEventCreate");
+        }
+    }
+    *plan_out = p;
+    return DTW_OK;
+}
+
+int dtw_plan_execute(dtw_plan p, void *stream) {
+    if (!p) return fail(DTW_ERR_INVALID_ARG, "plan is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = launch_stage(p->d_src, p->d_ser, p->ws, p->nseries, s);
+    if (e != hipSuccess) return hip_fail(e, "staging kernel launch");
+    if (p->ev0 && (e = hipEventRecord(p->ev0, s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+    for (const LaneGroup &g : p->lane_groups) {
+        e = launch_lane(g.W, p->ws, p->d_ser, p->d_ds, p->d_lane + g.begin, g.count, s);
+        if (e != hipSuccess) return hip_fail(e, "lane-band kernel launch");
+    }
+    for (const WaveGroup &g : p->wave_groups) {
+        e = launch_wave(g.H, g.banded, p->accum, p->ws, p->d_ser, p->d_ds, p->d_wave + g.begin, g.count, s);
+        if (e != hipSuccess) return hip_fail(e, "wavefront kernel launch");
+    }
+    if (p->ev1) {
+        if ((e = hipEventRecord(p->ev1, s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+        p->timed_once = true;
+    }
+    return DTW_OK;
+}
+
+int dtw_plan_last_kernel_ms(dtw_plan p, float *ms) {
+    if (!p || !ms) return fail(DTW_ERR_INVALID_ARG, "plan or ms is NULL");
+    if (!p->ev1 || !p->timed_once) return fail(DTW_ERR_INVALID_ARG, "plan was not created with DTW_FLAG_TIMING or never executed");
+    hipError_t e = hipEventSynchronize(p->ev1);
+    if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+    e = hipEventElapsedTime(ms, p->ev0, p->ev1);
+    if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+    return DTW_OK;
+}
+
+int dtw_plan_info(dtw_plan p, dtw_plan_stats *stats) {
+    if (!p || !stats) return fail(DTW_ERR_INVALID_ARG, "plan or stats is NULL");
+    *stats = p->stats;
+    return DTW_OK;
+}
+
+int dtw_plan_destroy(dtw_plan p) {
+    if (!p) return fail(DTW_ERR_INVALID_ARG, "plan is NULL");
+    destroy_plan(p);
+    return DTW_OK;
+}
+
+int dtw_pairwise_ex(const dtw_dataset *ds, const dtw_options *opt) {
+    g_err.clear();
+    if (!ds) return fail(DTW_ERR_INVALID_ARG, "dataset is NULL");
+    int rc = validate_options(opt);
+    if (rc) return rc;
+    if ((rc = validate_dataset(*ds, 0))) return rc;
+    if (ds->N < 2) return DTW_OK;  // nothing to write, no HIP call
+    dtw_options o{};
+    if (opt) o = *opt;
+    o.flags = 0;
+    dtw_plan p = nullptr;
+    rc = dtw_plan_create(&p, ds, 1, &o);
+    if (rc) return rc;
+    rc = dtw_plan_execute(p, o.stream);
+    hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(o.stream));
+    destroy_plan(p);
+    if (rc) return rc;
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    return DTW_OK;
+}
+
+int dtw_pairwise(const float *series, const int32_t *lengths, const int64_t *offsets, int32_t N, int32_t window,
+                 float *out_condensed) {
+    dtw_dataset d{series, lengths, offsets, N, window, out_condensed};
+    return dtw_pairwise_ex(&d, nullptr);
+}
+
+}  // extern "C"

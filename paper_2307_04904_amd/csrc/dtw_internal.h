@@ -1,0 +1,63 @@
+// Internal layout shared by the host planner (dtw_api.hip) and the kernels
+// (dtw_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dtwmi {
+
+// Padding (in FP32 elements) written before and after every staged series.
+// Pad cells hold +inf, so a read of y outside [0, m) yields an inadmissible
+// (+inf) local cost without any branch.  Kernels rely on:
+//   lane-band kernel: reads y[i-B .. i+B] with B <= 63, x[0 .. L+7];
+//   wavefront kernel: reads y[s-lane] for s in [0, m+64] and lane in [0,63].
+constexpr int kPad = 128;
+constexpr int kLaneMaxW = 127;   // widest band (2*B+1) of the lane-band kernel
+constexpr int kWaveMaxRows = 4096;  // 64 lanes x 64 rows
+
+struct SeriesSrc {     // where a series lives in the caller's buffer
+    const void *base;  // device pointer of the dataset buffer
+    int64_t off;       // element offset
+    int32_t len;
+    int32_t dtype;     // dtw_dtype
+};
+
+struct SeriesInfo {    // where a series lives in the staged FP32 workspace
+    int64_t pstart;    // index of element 0 (16-byte aligned); pads at [-kPad, 0) and [len, len+kPad)
+    int32_t len;
+    int32_t pad_;
+};
+
+struct DatasetInfo {
+    float *out;        // condensed output of this dataset
+    int32_t N;
+    int32_t window;    // as given (< 0 = none)
+    int32_t L;         // common length if all series are equal, else -1
+    int32_t series_base;  // global index of the dataset's first series
+};
+
+// Lane-band work item: one wavefront evaluates the pairs
+// (a, (a + d0 + lane) mod N) for lane < cnt, all series of length L.
+struct LaneItem {
+    int32_t ds, a, d0, cnt;
+};
+
+// Wavefront work item: one wavefront evaluates one pair; `rows` is the series
+// spread over the lanes (the shorter one), `cols` the one swept step by step.
+struct WaveItem {
+    int32_t ds, rows, cols, band;  // band = max(w, |n-m|), or -1 for none
+};
+
+// Kernel launchers (dtw_kernels.hip).  All asynchronous on `stream`.
+hipError_t launch_stage(const SeriesSrc *src, const SeriesInfo *ser, float *ws, int32_t nseries,
+                        hipStream_t stream);
+bool lane_width_supported(int W);
+hipError_t launch_lane(int W, const float *ws, const SeriesInfo *ser, const DatasetInfo *dsi,
+                       const LaneItem *items, int64_t n_items, hipStream_t stream);
+int wave_rows_per_lane(int n);  // smallest instantiated H with 64*H >= n, or 0
+hipError_t launch_wave(int H, bool banded, int accum, const float *ws, const SeriesInfo *ser,
+                       const DatasetInfo *dsi, const WaveItem *items, int64_t n_items,
+                       hipStream_t stream);
+
+}  // namespace dtwmi

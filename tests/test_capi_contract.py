@@ -1,0 +1,110 @@
+"""C-ABI contract checks that need no GPU: the library loads, exports every
+symbol the header declares, and rejects bad arguments on the host before any
+HIP call."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2307_04904_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dtwmi.h")
+
+FAKE_DEV = 0x1000  # never dereferenced: validation fails first
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(dtw_\w+)\s*\(", text, flags=re.M)))
+
+
+def test_header_and_exports_agree():
+    names = declared_functions()
+    assert len(names) >= 10
+    lib = ctypes.CDLL(B.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(B.EXPORTED)
+
+
+def test_version():
+    assert B.dtw_version() == 100
+
+
+@pytest.mark.parametrize("n,m,w", [(512, 512, 51), (256, 256, 25), (4096, 4096, -1), (64, 64, -1),
+                                   (100, 300, 0), (300, 100, 17), (1, 1, 0), (1, 50, 3), (2048, 64, 102)])
+def test_band_cells_matches_oracle(n, m, w):
+    assert B.dtw_band_cells(n, m, w) == oracle.band_cells(n, m, w)
+
+
+def test_band_cells_sweep():
+    rng = np.random.default_rng(0)
+    for _ in range(300):
+        n, m = rng.integers(1, 200, size=2)
+        w = int(rng.integers(-1, 220))
+        assert B.dtw_band_cells(n, m, w) == oracle.band_cells(n, m, w)
+
+
+def _call_ex(lengths, offsets, N=None, window=-1, series=FAKE_DEV, out=FAKE_DEV, dtype=0, accum=0, kernel=0, flags=0):
+    lib = B.load()
+    ln = np.ascontiguousarray(lengths, dtype=np.int32)
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    d = B.dtw_dataset()
+    d.series = ctypes.c_void_p(series)
+    d.lengths = ln.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)) if lengths is not None else None
+    d.offsets = off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)) if offsets is not None else None
+    d.N = len(ln) if N is None else N
+    d.window = window
+    d.out_condensed = ctypes.c_void_p(out)
+    o = B.dtw_options()
+    o.dtype, o.accum, o.kernel, o.flags = dtype, accum, kernel, flags
+    rc = lib.dtw_pairwise_ex(ctypes.byref(d), ctypes.byref(o))
+    return rc, B.dtw_last_error()
+
+
+def test_invalid_arguments_rejected_on_host():
+    ok_len, ok_off = [4, 4, 4], [0, 4, 8]
+    assert _call_ex(ok_len, ok_off, N=-1)[0] == B.DTW_ERR_INVALID_ARG
+    assert _call_ex([4, 0, 4], ok_off)[0] == B.DTW_ERR_INVALID_ARG
+    assert _call_ex(ok_len, [0, -4, 8])[0] == B.DTW_ERR_INVALID_ARG
+    rc, msg = _call_ex(ok_len, ok_off, series=0)
+    assert rc == B.DTW_ERR_INVALID_ARG and "series" in msg
+    rc, msg = _call_ex(ok_len, ok_off, out=0)
+    assert rc == B.DTW_ERR_INVALID_ARG and "out_condensed" in msg
+    assert _call_ex(ok_len, ok_off, dtype=7)[0] == B.DTW_ERR_INVALID_ARG
+    assert _call_ex(ok_len, ok_off, accum=3)[0] == B.DTW_ERR_INVALID_ARG
+    assert _call_ex(ok_len, ok_off, kernel=9)[0] == B.DTW_ERR_INVALID_ARG
+    assert _call_ex(ok_len, ok_off, flags=8)[0] == B.DTW_ERR_INVALID_ARG
+    lib = B.load()
+    assert lib.dtw_pairwise_ex(None, None) == B.DTW_ERR_INVALID_ARG
+    assert lib.dtw_plan_destroy(None) == B.DTW_ERR_INVALID_ARG
+    assert lib.dtw_plan_execute(None, None) == B.DTW_ERR_INVALID_ARG
+    assert lib.dtw_band_cells(3, 3, 0, None) == B.DTW_ERR_INVALID_ARG
+
+
+def test_fewer_than_two_series_is_a_no_op():
+    # no HIP call is made: this passes on a machine without a GPU
+    assert _call_ex([], [], series=0, out=0)[0] == B.DTW_OK
+    assert _call_ex([5], [0], series=0, out=0)[0] == B.DTW_OK
+
+
+def test_unsupported_requests_rejected_on_host():
+    # forcing the lane-band kernel on unequal lengths
+    rc, msg = _call_ex([4, 5, 4], [0, 4, 9], kernel=1)
+    assert rc == B.DTW_ERR_UNSUPPORTED and "lane-band" in msg
+    # lane-band kernel with Kahan accumulation
+    assert _call_ex([4, 4], [0, 4], kernel=1, accum=1)[0] == B.DTW_ERR_UNSUPPORTED
+    # both series of a pair longer than the wavefront kernel covers
+    rc, msg = _call_ex([5000, 5000], [0, 5000])
+    assert rc == B.DTW_ERR_UNSUPPORTED and "4096" in msg
+
+
+def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
+    monkeypatch.setattr(B, "_lib", None)
+    with pytest.raises(B.DtwError):
+        B.load(str(tmp_path / "missing.so"))

@@ -1,0 +1,190 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances: relative error <= 1e-5 for FP32 accumulation (plain and Kahan)
+on FP32 or 16-bit stored inputs, compared with the oracle run on the same
+stored values; the FP64 mode must equal the oracle rounded once to FP32.
+A reference value of exactly 0 must come out exactly 0.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2307_04904_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+REL_TOL = 1e-5
+
+
+def _gpu():
+    from paper_2307_04904_amd import binding
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a visible GPU")
+    return binding
+
+
+def oracle_pairs(ds, pi, pj):
+    vals = synth.stored_as_f64(ds)
+    out, _ = oracle.dtw_pairs(vals, ds.offsets, ds.lengths, pi, pj, ds.window)
+    return out
+
+
+def condensed(pi, pj, N):
+    pi = np.asarray(pi, dtype=np.int64)
+    pj = np.asarray(pj, dtype=np.int64)
+    return pi * N - pi * (pi + 1) // 2 + (pj - pi - 1)
+
+
+def sample_pairs(N, k, seed):
+    rng = np.random.default_rng(seed)
+    i = rng.integers(0, N, size=4 * k)
+    j = rng.integers(0, N, size=4 * k)
+    keep = i != j
+    a = np.minimum(i, j)[keep][:k]
+    b = np.maximum(i, j)[keep][:k]
+    # always include the first and last pairs
+    a = np.concatenate([[0, N - 2], a]).astype(np.int32)
+    b = np.concatenate([[1, N - 1], b]).astype(np.int32)
+    return a, b
+
+
+def assert_close(got, ref, tol=REL_TOL, what=""):
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    assert got.shape == ref.shape
+    assert np.all(np.isfinite(got)), what + ": non-finite output"
+    zero = ref == 0.0
+    assert np.all(got[zero] == 0.0), what + ": reference 0 not reproduced exactly"
+    rel = np.abs(got[~zero] - ref[~zero]) / ref[~zero]
+    worst = float(rel.max()) if rel.size else 0.0
+    assert worst <= tol, "%s: max rel err %.3e > %.1e (mean %.3e)" % (what, worst, tol, float(rel.mean()))
+    return worst
+
+
+def run(ds, **kw):
+    B = _gpu()
+    out = B.pairwise(ds, **kw)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+# ---------------------------------------------------------------- small cases, every pair
+
+@pytest.mark.parametrize("kernel", ["auto", "lane", "wave"])
+def test_smallest_config_all_pairs(kernel):
+    ds = synth.config1()
+    got = run(ds, kernel=kernel)
+    pi, pj = oracle.all_pairs_list(ds.N)
+    assert_close(got, oracle_pairs(ds, pi, pj), what="20x64 full " + kernel)
+
+
+@pytest.mark.parametrize("window", [-1, 0, 1, 5, 40])
+def test_ragged_lengths_wavefront(window):
+    # lengths 1..300 span strip heights 1..8, several ragged tails and both orientations
+    ds = synth.small_random(seed=100 + max(window, 0), N=23, len_lo=1, len_hi=300, window=window)
+    ds.lengths[0] = 1
+    got = run(ds)
+    pi, pj = oracle.all_pairs_list(ds.N)
+    assert_close(got, oracle_pairs(ds, pi, pj), what="ragged w=%d" % window)
+
+
+@pytest.mark.parametrize("window", [0, 3, 17, 36, 63, -1])
+def test_equal_lengths_both_kernels(window):
+    # N=150: every series has 74-75 partners -> one full and one ragged 64-lane item each
+    ds = synth.small_random(seed=7, N=150, len_lo=37, len_hi=37, window=window)
+    lane = run(ds, kernel="lane")
+    wave = run(ds, kernel="wave")
+    pi, pj = oracle.all_pairs_list(ds.N)
+    ref = oracle_pairs(ds, pi, pj)
+    assert_close(lane, ref, what="lane w=%d" % window)
+    assert_close(wave, ref, what="wave w=%d" % window)
+    # same per-cell arithmetic (sub, min of three, fused multiply-add) in both families
+    assert np.array_equal(lane, wave)
+
+
+def test_long_strips_and_unequal_lengths():
+    # pairs whose shorter series needs 12..64 rows per lane, window active on some
+    rng = np.random.default_rng(5)
+    lens = [700, 1500, 2900, 4096, 3100, 64, 1]
+    series = [synth.random_walk(rng, L) for L in lens]
+    for w in (-1, 150):
+        ds = synth.pack(series, "long", w)
+        got = run(ds)
+        pi, pj = oracle.all_pairs_list(ds.N)
+        assert_close(got, oracle_pairs(ds, pi, pj), what="long w=%d" % w)
+
+
+def test_single_point_series_and_two_series():
+    ds = synth.pack([np.array([0.5]), np.array([-1.0])], "tiny", 0)
+    got = run(ds)
+    assert got.tolist() == [2.25]
+    ds = synth.pack([np.array([0.5, 1.0, 2.0]), np.array([-1.0])], "tiny2", -1)
+    assert run(ds, kernel="wave").tolist() == [2.25 + 4.0 + 9.0]
+
+
+# ---------------------------------------------------------------- invariants
+
+def test_identical_series_give_exact_zero():
+    rng = np.random.default_rng(11)
+    base = [synth.random_walk(rng, 96) for _ in range(40)]
+    series = base + base  # series s and s+40 are identical
+    for kernel in ("lane", "wave"):
+        ds = synth.pack(series, "dup", 9)
+        got = run(ds, kernel=kernel)
+        k = condensed(np.arange(40), np.arange(40) + 40, 80)
+        assert np.all(got[k] == 0.0), kernel
+        assert np.all(got[np.setdiff1d(np.arange(len(got)), k)] > 0.0)
+
+
+@pytest.mark.parametrize("kernel", ["lane", "wave"])
+def test_symmetry_bitwise(kernel):
+    ds = synth.small_random(seed=3, N=90, len_lo=50, len_hi=50, window=6)
+    rev = synth.pack([ds.series(s).astype(np.float64) for s in range(ds.N)][::-1], "rev", 6)
+    a = run(ds, kernel=kernel)
+    b = run(rev, kernel=kernel)
+    pi, pj = oracle.all_pairs_list(ds.N)
+    assert np.array_equal(a, b[condensed(ds.N - 1 - pj, ds.N - 1 - pi, ds.N)])
+
+
+def test_window_monotone_bitwise():
+    base = synth.small_random(seed=4, N=40, len_lo=80, len_hi=80)
+    prev = None
+    for w in [0, 1, 2, 5, 10, 30, 63, -1]:
+        ds = synth.pack([base.series(s).astype(np.float64) for s in range(base.N)], "m", w)
+        got = run(ds, kernel="wave" if w > 63 or w < 0 else "auto")
+        if prev is not None:
+            assert np.all(got <= prev), w
+        prev = got
+
+
+# ---------------------------------------------------------------- full-size workloads, sampled
+
+def test_banded_1000x512_sampled():
+    ds = synth.config2()
+    got = run(ds)
+    assert not np.any(np.isnan(got)), "some pair was never written"
+    pi, pj = sample_pairs(ds.N, 3000, 1)
+    assert_close(got[condensed(pi, pj, ds.N)], oracle_pairs(ds, pi, pj), what="1000x512 w=51")
+
+
+def test_many_short_8000x256_sampled():
+    ds = synth.config5()
+    got = run(ds)
+    assert not np.any(np.isnan(got)), "some pair was never written"
+    pi, pj = sample_pairs(ds.N, 3000, 2)
+    assert_close(got[condensed(pi, pj, ds.N)], oracle_pairs(ds, pi, pj), what="8000x256 w=25")
+
+
+@pytest.mark.parametrize("dtype,accum", [("f32", "plain"), ("f32", "kahan"), ("f32", "fp64"),
+                                         ("bf16", "kahan"), ("f16", "kahan"), ("bf16", "plain")])
+def test_long_series_precision_modes(dtype, accum):
+    ds = synth.config3(dtype=dtype, N=500)
+    got = run(ds, accum=accum)
+    pi, pj = sample_pairs(ds.N, 24, 3)
+    ref = oracle_pairs(ds, pi, pj)
+    g = got[condensed(pi, pj, ds.N)]
+    if accum == "fp64":
+        assert np.array_equal(g, ref.astype(np.float32)), "FP64 mode must equal the oracle rounded to FP32"
+    else:
+        assert_close(g, ref, what="500x4096 %s %s" % (dtype, accum))
