@@ -38,54 +38,73 @@ WORKLOADS = {
     "c5": "many short series: 8000 x 256, window 25",
     "c3": "long series: 500 x 4096, no window",
     "c1": "smallest: 20 x 64, no window",
+    "c4": "batched uneven: 64 datasets, N in 10..400, lengths in 64..2048, mixed windows, one plan",
 }
 
 
-def make_dataset(name):
+def make_datasets(name, dtype="f32"):
     from paper_2307_04904_amd import synth
-    return {"c1": synth.config1, "c2": synth.config2, "c3": synth.config3, "c5": synth.config5}[name]()
+    if name == "c4":
+        return synth.config4()
+    if name == "c3":
+        return [synth.config3(dtype=dtype)]
+    return [{"c1": synth.config1, "c2": synth.config2, "c3": synth.config3, "c5": synth.config5}[name]()]
 
 
-def cpu_baseline(ds, gpu_out, target_s):
-    """Time the FP64 oracle on a seeded sample of pairs (all host cores) and check the GPU on them."""
+def cpu_baseline(dsets, gpu_outs, target_s):
+    """Time the FP64 oracle on a seeded sample of pairs (all host cores) and check the GPU on them.
+
+    The sample draws pairs uniformly over all datasets' pairs; the oracle runs
+    dataset by dataset on all host cores.
+    """
     import oracle
     from paper_2307_04904_amd import synth
-    vals = synth.stored_as_f64(ds)
     rng = np.random.default_rng(12345)
-    N = ds.N
+    npairs = np.array([d.n_pairs for d in dsets], dtype=np.int64)
 
     def sample(k):
-        i = rng.integers(0, N, size=3 * k)
-        j = rng.integers(0, N, size=3 * k)
-        keep = i != j
-        return np.minimum(i, j)[keep][:k].astype(np.int32), np.maximum(i, j)[keep][:k].astype(np.int32)
+        which = rng.choice(len(dsets), size=k, p=npairs / npairs.sum())
+        out = []
+        for d, ds in enumerate(dsets):
+            c = int(np.count_nonzero(which == d))
+            if c == 0:
+                continue
+            i = rng.integers(0, ds.N, size=3 * c + 8)
+            j = rng.integers(0, ds.N, size=3 * c + 8)
+            keep = i != j
+            out.append((d, np.minimum(i, j)[keep][:c].astype(np.int32), np.maximum(i, j)[keep][:c].astype(np.int32)))
+        return out
 
-    def cells(pi, pj):
-        L = ds.lengths
-        if np.all(L == L[0]):
-            return oracle.band_cells(int(L[0]), int(L[0]), ds.window) * len(pi)
-        return sum(oracle.band_cells(int(L[a]), int(L[b]), ds.window) for a, b in zip(pi, pj))
+    def run(smp):
+        t0 = time.perf_counter()
+        refs, cells, threads = [], 0, 0
+        for d, pi, pj in smp:
+            ds = dsets[d]
+            ref, threads = oracle.dtw_pairs(synth.stored_as_f64(ds), ds.offsets, ds.lengths, pi, pj, ds.window)
+            refs.append(ref)
+            L = ds.lengths
+            cells += sum(oracle.band_cells(int(L[a]), int(L[b]), ds.window) for a, b in zip(pi, pj))
+        return time.perf_counter() - t0, refs, cells, threads
 
-    pi, pj = sample(256)
-    t0 = time.perf_counter()
-    oracle.dtw_pairs(vals, ds.offsets, ds.lengths, pi, pj, ds.window)
-    t_cal = time.perf_counter() - t0
-    k = int(min(ds.n_pairs, max(256, 256 * target_s / max(t_cal, 1e-3))))
-    pi, pj = sample(k)
-    t0 = time.perf_counter()
-    ref, threads = oracle.dtw_pairs(vals, ds.offsets, ds.lengths, pi, pj, ds.window)
-    t = time.perf_counter() - t0
-    c = cells(pi, pj)
-    kk = pi.astype(np.int64) * N - pi.astype(np.int64) * (pi + 1) // 2 + (pj - pi - 1)
-    g = gpu_out[kk].astype(np.float64)
-    nz = ref > 0
-    rel = np.abs(g[nz] - ref[nz]) / ref[nz]
+    t_cal, _, _, _ = run(sample(256))
+    k = int(min(npairs.sum(), max(256, 256 * target_s / max(t_cal, 1e-3))))
+    smp = sample(k)
+    t, refs, c, threads = run(smp)
+    rels, zero_bad, n = [], 0, 0
+    for (d, pi, pj), ref in zip(smp, refs):
+        N = dsets[d].N
+        kk = pi.astype(np.int64) * N - pi.astype(np.int64) * (pi + 1) // 2 + (pj - pi - 1)
+        g = gpu_outs[d][kk].astype(np.float64)
+        nz = ref > 0
+        rels.append(np.abs(g[nz] - ref[nz]) / ref[nz])
+        zero_bad += int(np.count_nonzero(g[~nz] != 0.0))
+        n += len(pi)
+    rel = np.concatenate(rels) if rels else np.zeros(0)
     return {
         "value": c / t / 1e9, "unit": "GCUPS", "cores": int(threads), "kind": "oracle",
-        "sample": "%d seeded random pairs of the same workload (%.3g admissible cells), FP64, %.1f s" % (len(pi), c, t),
-    }, {"pairs_checked": int(len(pi)), "max_rel_err": float(rel.max()) if rel.size else 0.0,
-        "mean_rel_err": float(rel.mean()) if rel.size else 0.0,
-        "zero_mismatch": int(np.count_nonzero(g[~nz] != 0.0))}
+        "sample": "%d seeded random pairs of the same workload (%.3g admissible cells), FP64, %.1f s" % (n, c, t),
+    }, {"pairs_checked": n, "max_rel_err": float(rel.max()) if rel.size else 0.0,
+        "mean_rel_err": float(rel.mean()) if rel.size else 0.0, "zero_mismatch": zero_bad}
 
 
 def main(argv=None):
@@ -95,8 +114,13 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--kernel", default="auto", choices=["auto", "lane", "wave"])
+    ap.add_argument("--accum", default="plain", choices=["plain", "kahan", "fp64"])
+    ap.add_argument("--dtype", default="f32", choices=["f32", "bf16", "f16"],
+                    help="storage type of the series (the long-series workload's precision study)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="target duration of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration-mb", type=float, default=0.0,
+                    help="only run 5 device-to-device copies of this many MiB (reference for HBM byte counters)")
     args = ap.parse_args(argv)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -107,13 +131,23 @@ def main(argv=None):
     import torch
     from paper_2307_04904_amd import binding
 
-    ds = make_dataset(args.workload)
+    if args.copy_calibration_mb > 0:
+        n = int(args.copy_calibration_mb * 2 ** 20) // 4
+        src = torch.rand(n, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_per_copy": 4 * n, "copies": 5}), flush=True)
+        return 0
+
+    dsets = make_datasets(args.workload, args.dtype)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    series = binding.device_series(ds, dev)
-    out = torch.full((ds.n_pairs,), float("nan"), dtype=torch.float32, device=dev)
-    plan = binding.Plan([(series, ds.lengths, ds.offsets, ds.window, out)], dtype=ds.dtype,
-                        kernel=args.kernel, timing=True)
+    series = [binding.device_series(ds, dev) for ds in dsets]
+    outs = [torch.full((max(1, ds.n_pairs),), float("nan"), dtype=torch.float32, device=dev) for ds in dsets]
+    plan = binding.Plan([(s_, ds.lengths, ds.offsets, ds.window, o) for s_, ds, o in zip(series, dsets, outs)],
+                        dtype=dsets[0].dtype, accum=args.accum, kernel=args.kernel, timing=True)
     info = plan.info()
     stream = torch.cuda.current_stream(dev)
 
@@ -152,11 +186,15 @@ def main(argv=None):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f64" if args.accum == "fp64" else "f32",
         "data": "synthetic",
-        "config": {"workload": ds.name, "description": WORKLOADS[args.workload], "N": ds.N,
-                   "length": int(ds.lengths.max()), "window": ds.window, "pairs": info["pairs"],
-                   "band_cells": cells, "swept_cells": info["computed_cells"], "kernel": args.kernel},
+        "config": {"workload": dsets[0].name if len(dsets) == 1 else args.workload + "_batched_64_datasets",
+                   "description": WORKLOADS[args.workload], "datasets": len(dsets),
+                   "N": [ds.N for ds in dsets] if len(dsets) > 1 else dsets[0].N,
+                   "length": int(max(ds.lengths.max() for ds in dsets)),
+                   "window": [ds.window for ds in dsets] if len(dsets) > 1 else dsets[0].window,
+                   "pairs": info["pairs"], "band_cells": cells, "swept_cells": info["computed_cells"],
+                   "kernel": args.kernel, "accum": args.accum, "storage": dsets[0].dtype},
         "pct_peak_cell_rate": round(100.0 * value / (PEAK_LANE_OPS_T * 1e3 / OPS_PER_CELL), 2),
         "roofline": {
             "bound": "alu",
@@ -173,8 +211,7 @@ def main(argv=None):
     }
     if not args.no_cpu_baseline:
         torch.cuda.synchronize(dev)
-        gpu_out = out.cpu().numpy()
-        base, check = cpu_baseline(ds, gpu_out, args.cpu_seconds)
+        base, check = cpu_baseline(dsets, [o.cpu().numpy() for o in outs], args.cpu_seconds)
         line["cpu_baseline"] = base
         line["gpu_vs_oracle_on_sample"] = check
     plan.destroy()

@@ -85,65 +85,78 @@ __global__ __launch_bounds__(256) void k_stage(const SeriesSrc *__restrict__ src
 // ---------------------------------------------------------------------------
 // Lane-band kernel.
 //
-// One band row: cells k = 0..W-1 in order, each using y[i-B+k] (wave-uniform,
-// so it comes from scalar loads into SGPRs).  The row is processed in chunks
-// of C cells; the next chunk's y values are requested before the current
-// chunk is computed and a scheduling barrier keeps the compiler from hoisting
-// every load of the row (which would exceed the SGPR file and spill).
-constexpr int kLaneChunk = 32;
+// Row i of the band holds cells k = 0..W-1 (column i-B+k), updated in place:
+//   new[k] = (x_i - y_{i-B+k})^2 + min3(old[k], old[k+1], new[k-1]).
+// R consecutive rows are swept together, row i+r lagging 2 cells behind row
+// i+r-1: at step t row i+r updates cell t-2r, which only reads cells row
+// i+r-1 finished at steps t-2 and t-1, so the R updates of a step are
+// independent (R chains of instruction-level parallelism per lane) and all
+// still happen in place.  Step t of row i+r uses y[i-B+t-r]: a window of
+// C+R-1 wave-uniform values per chunk of C steps, fetched into SGPRs with
+// scalar loads one chunk ahead; a scheduling barrier keeps the compiler from
+// hoisting the loads of a whole row (which would exceed the SGPR file).
+// A chunk whose columns all lie outside [0, L) is skipped with a wave-uniform
+// branch: cells left of column 0 are +inf and stay +inf, and cells right of
+// column L-1 are never read by an admissible cell.
+#ifndef DTWMI_LANE_ROWS
+#define DTWMI_LANE_ROWS 4
+#endif
+#ifndef DTWMI_LANE_CHUNK
+#define DTWMI_LANE_CHUNK 16
+#endif
+constexpr int kLaneRows = DTWMI_LANE_ROWS;
+constexpr int kLaneChunk = DTWMI_LANE_CHUNK;
 
-template <int W, int K>
-__device__ __forceinline__ void lane_cell(float (&st)[W], float xi, float yk) {
+template <int W>
+__device__ __forceinline__ void lane_cell(float (&st)[W], int k, float xi, float yk) {
     const float d = xi - yk;
     float t;
-    if constexpr (W == 1) {
+    if (W == 1) {
         t = st[0];
-    } else if constexpr (K == 0) {
+    } else if (k == 0) {
         t = fminf(st[0], st[1]);  // left of the band is +inf
-    } else if constexpr (K == W - 1) {
+    } else if (k == W - 1) {
         t = fminf(st[W - 1], st[W - 2]);  // up is outside the band
     } else {
-        t = min3f(st[K], st[K + 1], st[K - 1]);
+        t = min3f(st[k], st[k + 1], st[k - 1]);
     }
-    st[K] = fmaf(d, d, t);
+    st[k] = fmaf(d, d, t);
 }
 
-template <int W, int C0, int... T>
-__device__ __forceinline__ void lane_chunk(float (&st)[W], float xi, const float (&yv)[kLaneChunk],
-                                           std::integer_sequence<int, T...>) {
-    ((C0 + T < W ? lane_cell<W, (C0 + T < W ? C0 + T : 0)>(st, xi, yv[T]) : void()), ...);
-}
-
-template <int W, int C0>
-__device__ __forceinline__ void lane_load(float (&yv)[kLaneChunk], const float *__restrict__ yw) {
+// One chunk (steps CH*C .. CH*C+C-1) of a group of R rows starting at row i,
+// then the following chunks.  ybase[v] = y[i-B-(R-1)+v]; ycur holds this
+// chunk's window on entry and the first window of the next group (read from
+// ynext) on exit.  col0 = i-B is the column of cell 0 of row i.
+template <int W, int R, int C, int CH>
+__device__ __forceinline__ void lane_group(float (&st)[W], const float (&x)[R], const float *__restrict__ ybase,
+                                           const float *__restrict__ ynext, float (&ycur)[C + R - 1], int col0,
+                                           int L) {
+    constexpr int T = W + 2 * (R - 1), NY = C + R - 1, NCH = (T + C - 1) / C, T0 = CH * C;
+    float ynxt[NY];
 #pragma unroll
-    for (int t = 0; t < kLaneChunk; ++t)
-        if (C0 + t < W) yv[t] = yw[C0 + t];
-}
-
-// Process row i (x value xi, window yw[k] = y[i-B+k]); ycur holds chunk 0 of
-// this row on entry and chunk 0 of the next row (window ynext) on exit.
-template <int W, int C0>
-__device__ __forceinline__ void lane_row_from(float (&st)[W], float xi, const float *__restrict__ yw,
-                                              const float *__restrict__ ynext, float (&ycur)[kLaneChunk]) {
-    float ynxt[kLaneChunk];
-    if constexpr (C0 + kLaneChunk < W) {
-        lane_load<W, C0 + kLaneChunk>(ynxt, yw);
-    } else {
-        lane_load<W, 0>(ynxt, ynext);
-    }
+    for (int u = 0; u < NY; ++u) ynxt[u] = (CH + 1 < NCH) ? ybase[T0 + C + u] : ynext[u];
     __builtin_amdgcn_sched_barrier(0);
-    lane_chunk<W, C0>(st, xi, ycur, std::make_integer_sequence<int, kLaneChunk>{});
+    const bool live = (col0 + T0 + C - 1 >= 0) && (col0 + T0 - (R - 1) < L);
+    if (live) {
 #pragma unroll
-    for (int t = 0; t < kLaneChunk; ++t) ycur[t] = ynxt[t];
-    if constexpr (C0 + kLaneChunk < W) lane_row_from<W, C0 + kLaneChunk>(st, xi, yw, ynext, ycur);
+        for (int u = 0; u < C; ++u) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int p = T0 + u - 2 * r;
+                if (p >= 0 && p < W) lane_cell<W>(st, p, x[r], ycur[u + R - 1 - r]);
+            }
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < NY; ++u) ycur[u] = ynxt[u];
+    if constexpr (CH + 1 < NCH) lane_group<W, R, C, CH + 1>(st, x, ybase, ynext, ycur, col0, L);
 }
 
 template <int W>
 __global__ __launch_bounds__(64) void k_lane(const float *__restrict__ ws, const SeriesInfo *__restrict__ ser,
                                              const DatasetInfo *__restrict__ dsi,
                                              const LaneItem *__restrict__ items) {
-    constexpr int B = (W - 1) / 2;
+    constexpr int B = (W - 1) / 2, R = kLaneRows, C = kLaneChunk;
     const LaneItem it = items[blockIdx.x];
     const DatasetInfo D = dsi[it.ds];
     const int lane = threadIdx.x;
@@ -151,7 +164,7 @@ __global__ __launch_bounds__(64) void k_lane(const float *__restrict__ ws, const
     int bl = it.a + it.d0 + lane;
     bl = bl >= D.N ? bl - D.N : bl;
     if (!valid) bl = it.a;  // idle lanes recompute a valid pair and store nothing
-    const float *__restrict__ ycol = ws + ser[D.series_base + it.a].pstart - B;
+    const float *__restrict__ ycol = ws + ser[D.series_base + it.a].pstart - B;  // ycol[v] = y[v-B]
     const float *__restrict__ xrow = ws + ser[D.series_base + bl].pstart;
     const int L = D.L;
 
@@ -160,15 +173,31 @@ __global__ __launch_bounds__(64) void k_lane(const float *__restrict__ ws, const
     for (int k = 0; k < W; ++k) st[k] = kInf;
     st[B] = 0.0f;  // c(0,0) of the 1-based recurrence, seen as the diagonal of cell (1,1)
 
-    float ycur[kLaneChunk];
-    lane_load<W, 0>(ycur, ycol);
-    // x of the next two rows is requested ahead (reads stay inside the pad).
-    float x0 = xrow[0], x1 = xrow[1];
-    for (int i = 0; i < L; ++i) {
-        const float x2 = xrow[i + 2];
-        lane_row_from<W, 0>(st, x0, ycol + i, ycol + i + 1, ycur);
-        x0 = x1;
-        x1 = x2;
+    int i = 0;
+    if (L >= R) {
+        float ycur[C + R - 1];
+#pragma unroll
+        for (int u = 0; u < C + R - 1; ++u) ycur[u] = ycol[u - (R - 1)];
+        float x[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) x[r] = xrow[r];
+        for (; i + R <= L; i += R) {
+            float xn[R];  // next group's x, requested one group ahead (stays inside the pad)
+#pragma unroll
+            for (int r = 0; r < R; ++r) xn[r] = xrow[i + R + r];
+            lane_group<W, R, C, 0>(st, x, ycol + i - (R - 1), ycol + i + 1, ycur, i - B, L);
+#pragma unroll
+            for (int r = 0; r < R; ++r) x[r] = xn[r];
+        }
+    }
+    if constexpr (R > 1) {
+        for (; i < L; ++i) {  // rows left over when R does not divide L
+            float ycur[C];
+#pragma unroll
+            for (int u = 0; u < C; ++u) ycur[u] = ycol[i + u];
+            const float x1[1] = {xrow[i]};
+            lane_group<W, 1, C, 0>(st, x1, ycol + i, ycol + i + 1, ycur, i - B, L);
+        }
     }
 
     if (valid) {
