@@ -75,16 +75,26 @@ def cpu_baseline(dsets, gpu_outs, target_s):
             out.append((d, np.minimum(i, j)[keep][:c].astype(np.int32), np.maximum(i, j)[keep][:c].astype(np.int32)))
         return out
 
+    # every dataset's series in one buffer, so one oracle call spans all sampled pairs
+    vals = np.concatenate([synth.stored_as_f64(ds) for ds in dsets])
+    base = np.cumsum([0] + [len(ds.values) for ds in dsets])[:-1]
+    sbase = np.cumsum([0] + [ds.N for ds in dsets])[:-1]
+    offs = np.concatenate([ds.offsets + b for ds, b in zip(dsets, base)])
+    lens = np.concatenate([ds.lengths for ds in dsets])
+
     def run(smp):
+        pi = np.concatenate([sbase[d] + a for d, a, _ in smp]).astype(np.int32)
+        pj = np.concatenate([sbase[d] + b for d, _, b in smp]).astype(np.int32)
+        win = np.concatenate([np.full(len(a), dsets[d].window, dtype=np.int32) for d, a, _ in smp])
         t0 = time.perf_counter()
-        refs, cells, threads = [], 0, 0
-        for d, pi, pj in smp:
-            ds = dsets[d]
-            ref, threads = oracle.dtw_pairs(synth.stored_as_f64(ds), ds.offsets, ds.lengths, pi, pj, ds.window)
-            refs.append(ref)
-            L = ds.lengths
-            cells += sum(oracle.band_cells(int(L[a]), int(L[b]), ds.window) for a, b in zip(pi, pj))
-        return time.perf_counter() - t0, refs, cells, threads
+        ref, threads = oracle.dtw_pairs(vals, offs, lens, pi, pj, win)
+        t = time.perf_counter() - t0
+        cells = sum(oracle.band_cells(int(lens[a]), int(lens[b]), int(w_)) for a, b, w_ in zip(pi, pj, win))
+        refs, k = [], 0
+        for d, a, _ in smp:
+            refs.append(ref[k:k + len(a)])
+            k += len(a)
+        return t, refs, cells, threads
 
     t_cal, _, _, _ = run(sample(256))
     k = int(min(npairs.sum(), max(256, 256 * target_s / max(t_cal, 1e-3))))

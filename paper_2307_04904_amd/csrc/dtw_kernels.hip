@@ -271,10 +271,9 @@ __device__ __forceinline__ void load_rows(float (&x)[H], const WaveSetup &w) {
     }
 }
 
-template <int H, bool BANDED>
-__device__ __forceinline__ void wave_step_f32(int s, float yv, const float (&x)[H], const float (&O)[H],
-                                              float (&N)[H], float &up_in, float &diag_in,
-                                              const WaveSetup &w, int lane) {
+template <int H, bool BANDED, typename XT>
+__device__ __forceinline__ void wave_step_f32(int s, float yv, const XT &x, const float (&O)[H], float (&N)[H],
+                                              float &up_in, float &diag_in, const WaveSetup &w, int lane) {
     float diag = diag_in, up = up_in;
     const int off = w.rbase - (s - lane);
 #pragma unroll
@@ -293,35 +292,102 @@ __device__ __forceinline__ void wave_step_f32(int s, float yv, const float (&x)[
     up_in = recv;
 }
 
+// Window edges by row events.  With the skew "lane l at step s is at column
+// s-l", row r = l*H+h enters the window (column r-b) at step l(H+1)+h-b and
+// leaves it (column r+b+1) at step l(H+1)+h+b+1: at most one row enters and
+// one row leaves per step, and both the lane and the strip row of each event
+// are wave-uniform.  A row outside the window has its x replaced by 1e30 (its
+// local cost overflows to +inf), so the cell loop itself carries no test.
+// The x values live in a register vector so that the uniform row index of an
+// event becomes one indexed register move (s_set_gpr_idx) instead of a test
+// per cell.
+template <int H>
+struct XVec {
+    typedef float T __attribute__((ext_vector_type(H)));
+};
+
+struct BandEvents {
+    int le, he;  // next entry: lane, strip row (he == H: no entry this step)
+    int lx, hx;  // next exit
+    int b, n;
+
+    template <int H>
+    __device__ __forceinline__ void init(int band, int n_rows) {
+        b = band;
+        n = n_rows;
+        le = band / (H + 1);
+        he = band - le * (H + 1);
+        lx = 0;
+        hx = 0;
+    }
+
+    // Apply the events of step s, then advance to step s+1.
+    template <int H>
+    __device__ __forceinline__ void step(int s, typename XVec<H>::T &xe, const typename XVec<H>::T &xr, int lane) {
+        if (he < H && le < 64 && le * H + he < n && s - le > 0) {
+            const float cur = xe[he];
+            const float v = xr[he];
+            xe[he] = lane == le ? v : cur;
+        }
+        if (++he == H + 1) {
+            he = 0;
+            ++le;
+        }
+        if (s > b) {
+            if (hx < H && lx < 64 && lx * H + hx < n) {
+                const float cur = xe[hx];
+                xe[hx] = lane == lx ? kBig : cur;
+            }
+            if (++hx == H + 1) {
+                hx = 0;
+                ++lx;
+            }
+        }
+    }
+};
+
 template <int H, bool BANDED>
 __global__ __launch_bounds__(64) void k_wave_plain(const float *__restrict__ ws,
                                                    const SeriesInfo *__restrict__ ser,
                                                    const DatasetInfo *__restrict__ dsi,
                                                    const WaveItem *__restrict__ items) {
+    // window edges by row events up to 32 rows per lane; wider strips test every cell
+    constexpr bool EVENTS = BANDED && H <= 32;
+    constexpr bool PERCELL = BANDED && !EVENTS;
+    typedef typename XVec<H>::T xvec;
     const int lane = threadIdx.x;
     const WaveItem it = items[blockIdx.x];
     const WaveSetup w = wave_setup(H, ws, ser, dsi, it, lane);
-    float x[H], A[H], Bv[H];
-    load_rows<H>(x, w);
+    float xa[H], A[H], Bv[H];
+    load_rows<H>(xa, w);
+    xvec xr, x;
 #pragma unroll
     for (int h = 0; h < H; ++h) {
+        const int r = w.rbase + h;
+        xr[h] = xa[h];
+        x[h] = (!EVENTS || (r < w.n && r - w.band <= 0)) ? xa[h] : kBig;
         A[h] = kInf;
         Bv[h] = kInf;
     }
+    BandEvents ev;
+    if constexpr (EVENTS) ev.init<H>(w.band, w.n);
     float up_in = kInf;
     float diag_in = lane == 0 ? 0.0f : kInf;
     float y0 = w.yp[0], y1 = w.yp[1];
     int s = 0;
     for (; s + 2 <= w.S; s += 2) {
         const float y2 = w.yp[s + 2], y3 = w.yp[s + 3];
-        wave_step_f32<H, BANDED>(s, y0, x, A, Bv, up_in, diag_in, w, lane);
-        wave_step_f32<H, BANDED>(s + 1, y1, x, Bv, A, up_in, diag_in, w, lane);
+        if constexpr (EVENTS) ev.step<H>(s, x, xr, lane);
+        wave_step_f32<H, PERCELL>(s, y0, x, A, Bv, up_in, diag_in, w, lane);
+        if constexpr (EVENTS) ev.step<H>(s + 1, x, xr, lane);
+        wave_step_f32<H, PERCELL>(s + 1, y1, x, Bv, A, up_in, diag_in, w, lane);
         y0 = y2;
         y1 = y3;
     }
     float res;
     if (s < w.S) {
-        wave_step_f32<H, BANDED>(s, y0, x, A, Bv, up_in, diag_in, w, lane);
+        if constexpr (EVENTS) ev.step<H>(s, x, xr, lane);
+        wave_step_f32<H, PERCELL>(s, y0, x, A, Bv, up_in, diag_in, w, lane);
         res = pick<H>(Bv, w.hstar);
     } else {
         res = pick<H>(A, w.hstar);
