@@ -32,6 +32,8 @@ if ROOT not in sys.path:
 PEAK_LANE_OPS_T = 256 * 128 * 2.4e9 / 1e12          # 78.64
 PEAK_UNPACKED_LANE_OPS_T = 256 * 64 * 2.4e9 / 1e12  # 39.32
 OPS_PER_CELL = 3
+# profile summary (profiles/<label>*.md) holding the counter-based HBM traffic of a workload's DP kernel
+PROFILE_LABELS = {("c2", "auto", "plain", "f32"): "lane_band_W103_c2"}
 
 WORKLOADS = {
     "c2": "equal-length banded matrix: 1000 random walks x 512, window 51",
@@ -49,6 +51,26 @@ def make_datasets(name, dtype="f32"):
     if name == "c3":
         return [synth.config3(dtype=dtype)]
     return [{"c1": synth.config1, "c2": synth.config2, "c3": synth.config3, "c5": synth.config5}[name]()]
+
+
+def recorded_traffic(kernel_label):
+    """HBM bytes per launch recorded in profiles/ for the current kernel source, else None.
+
+    A profile file names the kernel source hash it was measured on
+    ("kernel_source_sha256: ...") and the scaled FETCH_SIZE + WRITE_SIZE total
+    ("traffic_bytes_per_launch: ..."); a changed source invalidates it.
+    """
+    import glob
+    import hashlib
+    src = os.path.join(ROOT, "paper_2307_04904_amd", "csrc", "dtw_kernels.hip")
+    cur = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    for path in glob.glob(os.path.join(ROOT, "profiles", kernel_label + "*.md")):
+        text = open(path).read()
+        h = [l.split(":", 1)[1].strip() for l in text.splitlines() if l.startswith("kernel_source_sha256:")]
+        t = [l.split(":", 1)[1].strip() for l in text.splitlines() if l.startswith("traffic_bytes_per_launch:")]
+        if h and t and h[0] == cur:
+            return int(t[0])
+    return None
 
 
 def cpu_baseline(dsets, gpu_outs, target_s):
@@ -215,7 +237,7 @@ def main(argv=None):
             "frac_of_unpacked_issue": round(achieved / PEAK_UNPACKED_LANE_OPS_T, 4),
             "kernel_ms": round(k_avg, 4),
             "ops_per_launch": OPS_PER_CELL * cells,
-            "traffic": None,
+            "traffic": recorded_traffic(PROFILE_LABELS.get((args.workload, args.kernel, args.accum, args.dtype), "-")),
         },
         "wall_s": round(wall, 3),
     }
