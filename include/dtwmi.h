@@ -25,9 +25,9 @@
  *   - All arguments are validated on the host before any HIP call.
  *   - Series values must be finite; results for NaN or inf inputs are
  *     unspecified.  The output is always FP32.
- *   - Series may have any length >= 1; the wavefront kernel covers the
- *     shorter series of a pair up to 4096 points, a longer shorter-series
- *     returns DTW_ERR_UNSUPPORTED.
+ *   - Series may have any length >= 1.  The shorter series of a pair may have
+ *     up to 32768 points with PLAIN accumulation and up to 16384 with KAHAN
+ *     or FP64; longer returns DTW_ERR_UNSUPPORTED.
  */
 #ifndef DTWMI_H
 #define DTWMI_H
@@ -59,8 +59,9 @@ typedef enum { DTW_ACC_PLAIN = 0, DTW_ACC_KAHAN = 1, DTW_ACC_FP64 = 2 } dtw_accu
 /* Kernel family; AUTO picks per dataset.  The others exist for tests/benches.
  *   LANE: one pair per lane, the band row kept in registers (all series of the
  *         dataset of equal length, 2*w+1 <= 127, PLAIN only).
- *   WAVE: one pair per 64-lane wavefront sweeping anti-diagonals, each lane
- *         owning a strip of rows (any lengths, any window, any accumulation). */
+ *   WAVE: one pair per workgroup of 1..16 wavefronts sweeping anti-diagonals,
+ *         each lane owning a strip of rows (any lengths, any window, any
+ *         accumulation). */
 typedef enum { DTW_KERNEL_AUTO = 0, DTW_KERNEL_LANE = 1, DTW_KERNEL_WAVE = 2 } dtw_kernel;
 
 /* One dataset: N series concatenated in one device buffer. */

@@ -78,10 +78,28 @@ struct LaneGroup {
 };
 
 struct WaveGroup {
-    int H;
+    StripShape shape;
     bool banded;
     int64_t begin, count;
 };
+
+// Strip shape for a pair whose shorter series has n points: the instantiated
+// shape of smallest row capacity 64*H*G >= n ({0,0} if none is large enough).
+StripShape pick_strip(int accum, int n) {
+    StripShape shapes[64];
+    const int k = strip_shapes(accum, shapes, 64);
+    for (int i = 0; i < k && i < 64; ++i)
+        if (64 * shapes[i].H * shapes[i].G >= n) return shapes[i];
+    return StripShape{0, 0};
+}
+
+int max_strip_rows(int accum) {
+    StripShape shapes[64];
+    const int k = strip_shapes(accum, shapes, 64);
+    int best = 0;
+    for (int i = 0; i < k && i < 64; ++i) best = std::max(best, 64 * shapes[i].H * shapes[i].G);
+    return best;
+}
 
 }  // namespace
 
@@ -243,16 +261,18 @@ int dtw_plan_create(dtw_plan *plan_out, const dtw_dataset *ds, int32_t n_dataset
                     const bool swap = nj < ni;
                     const int32_t rows = swap ? j : i, cols = swap ? i : j;
                     const int32_t n = std::min(ni, nj), m = std::max(ni, nj);
-                    const int H = wave_rows_per_lane(n);
-                    if (!H)
+                    const StripShape sh = pick_strip(accum, n);
+                    if (!sh.H)
                         return fail(DTW_ERR_UNSUPPORTED,
                                     "dataset %d: pair (%d,%d) has both series longer than %d points", d, i, j,
-                                    kWaveMaxRows);
+                                    max_strip_rows(accum));
                     const int64_t b = effective_band(D.window, n, m);
                     const int64_t cells = band_cells(n, m, b);
                     st.band_cells += cells;
-                    st.computed_cells += (int64_t)64 * H * (m + (n - 1) / H);
-                    wave_by_kind[{H, b >= 0}].push_back({cells, WaveItem{d, rows, cols, (int32_t)b}});
+                    const int64_t lanes = (n - 1) / sh.H;  // last lane holding a row
+                    st.computed_cells += (int64_t)64 * sh.G * sh.H *
+                                         (m + lanes % 64 + (lanes / 64) * (64 + (sh.G > 1 ? 16 : 0)));
+                    wave_by_kind[{sh.H * 1000 + sh.G, b >= 0}].push_back({cells, WaveItem{d, rows, cols, (int32_t)b}});
                 }
             }
         }
@@ -271,13 +291,18 @@ int dtw_plan_create(dtw_plan *plan_out, const dtw_dataset *ds, int32_t n_dataset
         p->lane_groups.push_back(LaneGroup{kv.first, (int64_t)lane_items.size(), (int64_t)kv.second.size()});
         lane_items.insert(lane_items.end(), kv.second.begin(), kv.second.end());
     }
-    // Larger strips first; inside a group, larger pairs first.
-    for (auto it = wave_by_kind.rbegin(); it != wave_by_kind.rend(); ++it) {
+    // Larger strips first (by row capacity); inside a group, larger pairs first.
+    std::vector<std::map<std::pair<int, bool>, std::vector<std::pair<int64_t, WaveItem>>>::iterator> order;
+    for (auto it = wave_by_kind.begin(); it != wave_by_kind.end(); ++it) order.push_back(it);
+    std::stable_sort(order.begin(), order.end(), [](const auto &a, const auto &b) {
+        return (a->first.first / 1000) * (a->first.first % 1000) > (b->first.first / 1000) * (b->first.first % 1000);
+    });
+    for (auto it : order) {
         auto &v = it->second;
         std::stable_sort(v.begin(), v.end(), [](const std::pair<int64_t, WaveItem> &a,
                                                 const std::pair<int64_t, WaveItem> &b) { return a.first > b.first; });
-        p->wave_groups.push_back(WaveGroup{it->first.first, it->first.second, (int64_t)wave_items.size(),
-                                           (int64_t)v.size()});
+        const StripShape sh{it->first.first / 1000, it->first.first % 1000};
+        p->wave_groups.push_back(WaveGroup{sh, it->first.second, (int64_t)wave_items.size(), (int64_t)v.size()});
         for (auto &e : v) wave_items.push_back(e.second);
     }
     st.n_lane_items = static_cast<int32_t>(lane_items.size());
@@ -358,7 +383,7 @@ int dtw_plan_execute(dtw_plan p, void *stream) {
         if (e != hipSuccess) return hip_fail(e, "lane-band kernel launch");
     }
     for (const WaveGroup &g : p->wave_groups) {
-        e = launch_wave(g.H, g.banded, p->accum, p->ws, p->d_ser, p->d_ds, p->d_wave + g.begin, g.count, s);
+        e = launch_strip(p->accum, g.shape, g.banded, p->ws, p->d_ser, p->d_ds, p->d_wave + g.begin, g.count, s);
         if (e != hipSuccess) return hip_fail(e, "wavefront kernel launch");
     }
     if (p->ev1) {

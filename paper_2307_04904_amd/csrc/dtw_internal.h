@@ -11,10 +11,10 @@ namespace dtwmi {
 // Pad cells hold +inf, so a read of y outside [0, m) yields an inadmissible
 // (+inf) local cost without any branch.  Kernels rely on:
 //   lane-band kernel: reads y[i-B .. i+B] with B <= 63, x[0 .. L+7];
-//   wavefront kernel: reads y[s-lane] for s in [0, m+64] and lane in [0,63].
+//   wavefront kernels: clamp column reads into [-1, m].
 constexpr int kPad = 128;
 constexpr int kLaneMaxW = 127;   // widest band (2*B+1) of the lane-band kernel
-constexpr int kWaveMaxRows = 4096;  // 64 lanes x 64 rows
+
 
 struct SeriesSrc {     // where a series lives in the caller's buffer
     const void *base;  // device pointer of the dataset buffer
@@ -55,9 +55,15 @@ hipError_t launch_stage(const SeriesSrc *src, const SeriesInfo *ser, float *ws, 
 bool lane_width_supported(int W);
 hipError_t launch_lane(int W, const float *ws, const SeriesInfo *ser, const DatasetInfo *dsi,
                        const LaneItem *items, int64_t n_items, hipStream_t stream);
-int wave_rows_per_lane(int n);  // smallest instantiated H with 64*H >= n, or 0
-hipError_t launch_wave(int H, bool banded, int accum, const float *ws, const SeriesInfo *ser,
-                       const DatasetInfo *dsi, const WaveItem *items, int64_t n_items,
-                       hipStream_t stream);
+// Strip shapes of the wavefront kernels: H rows per lane, G wavefronts per pair
+// (a workgroup of 64*G lanes covers up to 64*H*G rows of the shorter series).
+struct StripShape {
+    int H, G;
+};
+// Instantiated shapes for an accumulation mode, in increasing row capacity;
+// returns their number (writes at most max_out of them).
+int strip_shapes(int accum, StripShape *out, int max_out);
+hipError_t launch_strip(int accum, StripShape shape, bool banded, const float *ws, const SeriesInfo *ser,
+                        const DatasetInfo *dsi, const WaveItem *items, int64_t n_items, hipStream_t stream);
 
 }  // namespace dtwmi

@@ -207,7 +207,19 @@ __global__ __launch_bounds__(64) void k_lane(const float *__restrict__ ws, const
 }
 
 // ---------------------------------------------------------------------------
-// Wavefront kernels.
+// Wavefront strip kernels: one pair per workgroup of G wavefronts.
+//
+// Lane l of wavefront g owns rows [(64g+l)H, (64g+l)H+H) of the row series
+// and at step s processes column s - l - g(64+D) (anti-diagonal skew).  Each
+// step updates a whole strip column: H cells in order, each cell's "up" being
+// the cell just computed above it.  The bottom cell goes to lane l+1 with a
+// DPP wave_shr:1 move; the previous step's received value is the diagonal.
+// Between wavefronts of one workgroup the bottom row of lane 63 is handed
+// over through an LDS ring: wavefront g lags wavefront g-1 by D = K extra
+// steps and the workgroup meets at a barrier every K steps, so a value is
+// always read at least one barrier after it was written.  State per lane is
+// 2H cells, ping-ponged over two unrolled steps.
+
 // v[h] for a wave-uniform runtime h, as a tree of selects on the bits of h
 // (a plain indexed read would push the whole register array to scratch).
 template <int H, typename T>
@@ -225,275 +237,268 @@ __device__ __forceinline__ T pick(const T (&v)[H], int h) {
     return t[0];
 }
 
+// Accumulation policies: cell(x, y, diag, up, left) evaluates Eq. (c).
+struct AccPlain {  // FP32: sub, min3, fused multiply-add
+    using T = float;
+    __device__ static T inf() { return kInf; }
+    __device__ static T zero() { return 0.0f; }
+    __device__ static T cell(float xe, float yv, T diag, T up, T left) {
+        const float d = xe - yv;
+        return fmaf(d, d, min3f(diag, up, left));
+    }
+    __device__ static float result(T v) { return v; }
+};
+
+// Kahan-compensated FP32: each cell carries (s, c) with the true value close
+// to s - c.  The min compares the running sums s (ties prefer diag, then up,
+// then left) and takes the compensation of the chosen predecessor; the local
+// cost is then added with Kahan's compensated step.  An unreachable cell (s =
+// +inf) gets c = NaN from inf - inf; that is harmless: a reachable cell has a
+// finite predecessor, fminf ignores quiet NaNs and NaN never compares equal,
+// so such a c is never selected.
+struct KahanCell {
+    float s, c;
+};
+struct AccKahan {
+    using T = KahanCell;
+    __device__ static T inf() { return {kInf, 0.0f}; }
+    __device__ static T zero() { return {0.0f, 0.0f}; }
+    __device__ static T cell(float xe, float yv, T diag, T up, T left) {
+        const float d = xe - yv;
+        const float q = d * d;
+        const float p = min3f(diag.s, up.s, left.s);
+        const float c1 = (p == up.s) ? up.c : left.c;
+        const float cs = (p == diag.s) ? diag.c : c1;
+        const float yk = q - cs;
+        const float t = p + yk;
+        return {t, (t - p) - yk};
+    }
+    __device__ static float result(T v) { return v.s < kInf ? v.s - v.c : v.s; }
+};
+
+// FP64: the operations of an IEEE double evaluation of Eq. (c) -- difference,
+// product, min of three, sum -- in that order, so the result equals the FP64
+// reference rounded once to FP32.  (An inadmissible cell's 1e30 x gives a
+// cost of ~1e60 instead of +inf; every admissible cell has an admissible
+// finite predecessor, so such values are never the minimum of one.)
+struct AccF64 {
+    using T = double;
+    __device__ static T inf() { return kInfD; }
+    __device__ static T zero() { return 0.0; }
+    __device__ static T cell(float xe, float yv, T diag, T up, T left) {
+        const double d = static_cast<double>(xe) - static_cast<double>(yv);
+        const double t = fmin(fmin(diag, up), left);
+        return d * d + t;
+    }
+    __device__ static float result(T v) { return static_cast<float>(v); }
+};
+
+__device__ __forceinline__ KahanCell lane_shift_down(KahanCell v, KahanCell fill) {
+    return {lane_shift_down(v.s, fill.s), lane_shift_down(v.c, fill.c)};
+}
+
+// Window edges by row events.  With the skew of this wavefront, a row of the
+// strip enters the window (column r-b) at step l(H+1)+h-be and leaves it
+// (column r+b+1) at step l(H+1)+h+bx+1, where l, h are the wave-local lane and
+// strip row and be, bx are the band shifted by the wavefront's offset: at most
+// one row enters and one row leaves per step, and the lane and strip row of
+// each event are wave-uniform.  A row outside the window has its x replaced
+// by 1e30 (its local cost overflows), so the cell loop itself carries no test.
+// x lives in a register vector so that an event's uniform row index becomes
+// one indexed register move (s_set_gpr_idx) instead of a test per cell.
+// (At least 16 elements: the compiler turns an indexed move into a chain of
+// compares and selects for smaller vectors.)
+template <int H>
+struct XVec {
+    typedef float T __attribute__((ext_vector_type(H < 16 ? 16 : H)));
+};
+
+struct RowCounter {  // t = s + off written as q(H+1) + h with 0 <= h <= H (q < 0 before the first event)
+    int q, h;
+    template <int H>
+    __device__ __forceinline__ void init(int off) {
+        q = off >= 0 ? off / (H + 1) : -((-off + H) / (H + 1));
+        h = off - q * (H + 1);
+    }
+    template <int H>
+    __device__ __forceinline__ void advance() {
+        if (++h == H + 1) {
+            h = 0;
+            ++q;
+        }
+    }
+};
+
+struct BandEvents {
+    RowCounter en, ex;
+    int nloc, col_shift;  // rows of the pair from this wavefront's first row; column = s - l - col_shift
+
+    template <int H>
+    __device__ __forceinline__ void init(int band, int n_rows, int wave, int D) {
+        const int row0 = wave * 64 * H;
+        nloc = n_rows - row0;
+        col_shift = wave * (64 + D);
+        const int shift = row0 + col_shift;
+        en.init<H>(band - shift);       // entry at step s: s + b - shift = l(H+1) + h
+        ex.init<H>(-band - shift - 1);  // exit at step s:  s - b - shift - 1 = l(H+1) + h
+    }
+
+    // Apply the events of step s (counters are at step s on entry), then advance.
+    template <int H>
+    __device__ __forceinline__ void step(int s, typename XVec<H>::T &xe, const typename XVec<H>::T &xr, int lane) {
+        if (en.h < H && en.q >= 0 && en.q < 64 && en.q * H + en.h < nloc && s - en.q - col_shift > 0) {
+            const float cur = xe[en.h];
+            const float v = xr[en.h];
+            xe[en.h] = lane == en.q ? v : cur;
+        }
+        en.advance<H>();
+        if (ex.h < H && ex.q >= 0 && ex.q < 64 && ex.q * H + ex.h < nloc) {
+            const float cur = xe[ex.h];
+            xe[ex.h] = lane == ex.q ? kBig : cur;
+        }
+        ex.advance<H>();
+    }
+};
+
 // True iff row rbase+h and column c are outside the window (off = rbase - c).
 __device__ __forceinline__ bool outside(int off, int h, int band) {
     const int o = off + h;
     return o > band || o < -band;
 }
 
-struct WaveSetup {
-    const float *xp;
-    const float *yp;  // yp[s] = y[s - lane]
-    int n, m, lstar, S, hstar, band, rbase;
-    float *out_at;
-};
+constexpr int kEpoch = 16;     // steps between workgroup barriers (multi-wavefront strips)
+constexpr int kRing = 64;      // LDS ring slots per wavefront boundary (>= 2*kEpoch + 2)
 
-__device__ __forceinline__ WaveSetup wave_setup(int H, const float *__restrict__ ws,
-                                                const SeriesInfo *__restrict__ ser,
-                                                const DatasetInfo *__restrict__ dsi,
-                                                const WaveItem &it, int lane) {
-    const DatasetInfo D = dsi[it.ds];
-    const SeriesInfo sr = ser[D.series_base + it.rows];
-    const SeriesInfo sc = ser[D.series_base + it.cols];
-    WaveSetup w;
-    w.n = sr.len;
-    w.m = sc.len;
-    w.xp = ws + sr.pstart;
-    w.yp = ws + sc.pstart - lane;
-    w.lstar = (w.n - 1) / H;
-    w.S = w.m + w.lstar;
-    w.hstar = (w.n - 1) - w.lstar * H;
-    w.band = it.band;
-    w.rbase = lane * H;
-    const int a = it.rows < it.cols ? it.rows : it.cols;
-    const int b = it.rows < it.cols ? it.cols : it.rows;
-    w.out_at = D.out + condensed_index(a, b, D.N);
-    return w;
-}
-
-template <int H>
-__device__ __forceinline__ void load_rows(float (&x)[H], const WaveSetup &w) {
-#pragma unroll
-    for (int h = 0; h < H; ++h) {
-        const int r = w.rbase + h;
-        const float v = w.xp[r < w.n ? r : w.n - 1];
-        x[h] = r < w.n ? v : 0.0f;  // rows past n are never read back into row n-1
-    }
-}
-
-template <int H, bool BANDED, typename XT>
-__device__ __forceinline__ void wave_step_f32(int s, float yv, const XT &x, const float (&O)[H], float (&N)[H],
-                                              float &up_in, float &diag_in, const WaveSetup &w, int lane) {
-    float diag = diag_in, up = up_in;
-    const int off = w.rbase - (s - lane);
+template <class ACC, int H, bool PERCELL, typename XT>
+__device__ __forceinline__ void strip_step(int c, float yv, const XT &x, const typename ACC::T (&O)[H],
+                                           typename ACC::T (&N)[H], typename ACC::T &up_in,
+                                           typename ACC::T &diag_in, int rbase, int band) {
+    using T = typename ACC::T;
+    T diag = diag_in, up = up_in;
+    const int off = rbase - c;
 #pragma unroll
     for (int h = 0; h < H; ++h) {
         float xe = x[h];
-        if constexpr (BANDED) xe = outside(off, h, w.band) ? kBig : xe;
-        const float d = xe - yv;
-        const float t = min3f(diag, up, O[h]);
-        const float v = fmaf(d, d, t);
+        if constexpr (PERCELL) xe = outside(off, h, band) ? kBig : xe;
+        const T v = ACC::cell(xe, yv, diag, up, O[h]);
         diag = O[h];
         up = v;
         N[h] = v;
     }
-    const float recv = lane_shift_down(N[H - 1], kInf);
-    diag_in = up_in;
-    up_in = recv;
 }
 
-// Window edges by row events.  With the skew "lane l at step s is at column
-// s-l", row r = l*H+h enters the window (column r-b) at step l(H+1)+h-b and
-// leaves it (column r+b+1) at step l(H+1)+h+b+1: at most one row enters and
-// one row leaves per step, and both the lane and the strip row of each event
-// are wave-uniform.  A row outside the window has its x replaced by 1e30 (its
-// local cost overflows to +inf), so the cell loop itself carries no test.
-// The x values live in a register vector so that the uniform row index of an
-// event becomes one indexed register move (s_set_gpr_idx) instead of a test
-// per cell.
-template <int H>
-struct XVec {
-    typedef float T __attribute__((ext_vector_type(H)));
-};
-
-struct BandEvents {
-    int le, he;  // next entry: lane, strip row (he == H: no entry this step)
-    int lx, hx;  // next exit
-    int b, n;
-
-    template <int H>
-    __device__ __forceinline__ void init(int band, int n_rows) {
-        b = band;
-        n = n_rows;
-        le = band / (H + 1);
-        he = band - le * (H + 1);
-        lx = 0;
-        hx = 0;
-    }
-
-    // Apply the events of step s, then advance to step s+1.
-    template <int H>
-    __device__ __forceinline__ void step(int s, typename XVec<H>::T &xe, const typename XVec<H>::T &xr, int lane) {
-        if (he < H && le < 64 && le * H + he < n && s - le > 0) {
-            const float cur = xe[he];
-            const float v = xr[he];
-            xe[he] = lane == le ? v : cur;
-        }
-        if (++he == H + 1) {
-            he = 0;
-            ++le;
-        }
-        if (s > b) {
-            if (hx < H && lx < 64 && lx * H + hx < n) {
-                const float cur = xe[hx];
-                xe[hx] = lane == lx ? kBig : cur;
-            }
-            if (++hx == H + 1) {
-                hx = 0;
-                ++lx;
-            }
-        }
-    }
-};
-
-template <int H, bool BANDED>
-__global__ __launch_bounds__(64) void k_wave_plain(const float *__restrict__ ws,
-                                                   const SeriesInfo *__restrict__ ser,
-                                                   const DatasetInfo *__restrict__ dsi,
-                                                   const WaveItem *__restrict__ items) {
-    // window edges by row events up to 32 rows per lane; wider strips test every cell
-    constexpr bool EVENTS = BANDED && H <= 32;
-    constexpr bool PERCELL = BANDED && !EVENTS;
-    typedef typename XVec<H>::T xvec;
-    const int lane = threadIdx.x;
-    const WaveItem it = items[blockIdx.x];
-    const WaveSetup w = wave_setup(H, ws, ser, dsi, it, lane);
-    float xa[H], A[H], Bv[H];
-    load_rows<H>(xa, w);
-    xvec xr, x;
-#pragma unroll
-    for (int h = 0; h < H; ++h) {
-        const int r = w.rbase + h;
-        xr[h] = xa[h];
-        x[h] = (!EVENTS || (r < w.n && r - w.band <= 0)) ? xa[h] : kBig;
-        A[h] = kInf;
-        Bv[h] = kInf;
-    }
-    BandEvents ev;
-    if constexpr (EVENTS) ev.init<H>(w.band, w.n);
-    float up_in = kInf;
-    float diag_in = lane == 0 ? 0.0f : kInf;
-    float y0 = w.yp[0], y1 = w.yp[1];
-    int s = 0;
-    for (; s + 2 <= w.S; s += 2) {
-        const float y2 = w.yp[s + 2], y3 = w.yp[s + 3];
-        if constexpr (EVENTS) ev.step<H>(s, x, xr, lane);
-        wave_step_f32<H, PERCELL>(s, y0, x, A, Bv, up_in, diag_in, w, lane);
-        if constexpr (EVENTS) ev.step<H>(s + 1, x, xr, lane);
-        wave_step_f32<H, PERCELL>(s + 1, y1, x, Bv, A, up_in, diag_in, w, lane);
-        y0 = y2;
-        y1 = y3;
-    }
-    float res;
-    if (s < w.S) {
-        if constexpr (EVENTS) ev.step<H>(s, x, xr, lane);
-        wave_step_f32<H, PERCELL>(s, y0, x, A, Bv, up_in, diag_in, w, lane);
-        res = pick<H>(Bv, w.hstar);
-    } else {
-        res = pick<H>(A, w.hstar);
-    }
-    if (lane == w.lstar) *w.out_at = res;
-}
-
-// FP64 accumulation: the same operations as an IEEE double evaluation of
-// Eq. (c) -- difference, product, min of three, sum -- in that order.
-template <int H, bool BANDED>
-__global__ __launch_bounds__(64) void k_wave_fp64(const float *__restrict__ ws,
-                                                  const SeriesInfo *__restrict__ ser,
+template <class ACC, int H, int G, bool BANDED>
+__global__ __launch_bounds__(64 * G) void k_strip(const float *__restrict__ ws, const SeriesInfo *__restrict__ ser,
                                                   const DatasetInfo *__restrict__ dsi,
                                                   const WaveItem *__restrict__ items) {
-    const int lane = threadIdx.x;
-    const WaveItem it = items[blockIdx.x];
-    const WaveSetup w = wave_setup(H, ws, ser, dsi, it, lane);
-    float x[H];
-    double st[H];
-    load_rows<H>(x, w);
-#pragma unroll
-    for (int h = 0; h < H; ++h) st[h] = kInfD;
-    double up_in = kInfD;
-    double diag_in = lane == 0 ? 0.0 : kInfD;
-    float ynext = w.yp[0];
-    for (int s = 0; s < w.S; ++s) {
-        const double yv = static_cast<double>(ynext);
-        ynext = w.yp[s + 1];
-        double diag = diag_in, up = up_in;
-        const int off = w.rbase - (s - lane);
-#pragma unroll
-        for (int h = 0; h < H; ++h) {
-            double xe = static_cast<double>(x[h]);
-            if constexpr (BANDED) xe = outside(off, h, w.band) ? kBigD : xe;
-            const double d = xe - yv;
-            const double t = fmin(fmin(diag, up), st[h]);
-            const double v = d * d + t;
-            diag = st[h];
-            st[h] = v;
-            up = v;
-        }
-        const double recv = lane_shift_down(st[H - 1], kInfD);
-        diag_in = up_in;
-        up_in = recv;
-    }
-    const double res = pick<H>(st, w.hstar);
-    if (lane == w.lstar) *w.out_at = static_cast<float>(res);
-}
+    using T = typename ACC::T;
+    constexpr bool EVENTS = BANDED && H <= 32;  // wider strips test every cell
+    constexpr bool PERCELL = BANDED && !EVENTS;
+    constexpr int D = G > 1 ? kEpoch : 0;
+    typedef typename XVec<H>::T xvec;
+    __shared__ T ring[G > 1 ? G - 1 : 1][kRing];
 
-// Kahan-compensated FP32: each cell carries (s, c) with the true value close
-// to s - c.  The min compares the running sums s (ties prefer diag, then up,
-// then left) and takes the compensation of the chosen predecessor; the local
-// cost is then added with Kahan's compensated step.  Unreachable (+inf) cells
-// carry c = 0.
-template <int H, bool BANDED>
-__global__ __launch_bounds__(64) void k_wave_kahan(const float *__restrict__ ws,
-                                                   const SeriesInfo *__restrict__ ser,
-                                                   const DatasetInfo *__restrict__ dsi,
-                                                   const WaveItem *__restrict__ items) {
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform within a wavefront
     const WaveItem it = items[blockIdx.x];
-    const WaveSetup w = wave_setup(H, ws, ser, dsi, it, lane);
-    float x[H], ss[H], cc[H];
-    load_rows<H>(x, w);
+    const DatasetInfo DI = dsi[it.ds];
+    const SeriesInfo sr = ser[DI.series_base + it.rows];
+    const SeriesInfo sc = ser[DI.series_base + it.cols];
+    const int n = sr.len, m = sc.len, band = it.band;
+    const float *__restrict__ xp = ws + sr.pstart;
+    const float *__restrict__ yp = ws + sc.pstart;
+    const int rbase = (wave * 64 + lane) * H;
+    const int skew = lane + wave * (64 + D);  // column = s - skew
+    const int Lf = (n - 1) / H, wf = Lf >> 6, lf = Lf & 63, hf = (n - 1) - Lf * H;
+    const int sfinal = (m - 1) + lf + wf * (64 + D);  // step computing cell (n-1, m-1)
+
+    float xa[H];
 #pragma unroll
     for (int h = 0; h < H; ++h) {
-        ss[h] = kInf;
-        cc[h] = 0.0f;
+        const int r = rbase + h;
+        const float v = xp[r < n ? r : n - 1];
+        xa[h] = r < n ? v : 0.0f;  // rows past n never feed row n-1
     }
-    float up_s = kInf, up_c = 0.0f;
-    float diag_s = lane == 0 ? 0.0f : kInf, diag_c = 0.0f;
-    float ynext = w.yp[0];
-    for (int s = 0; s < w.S; ++s) {
-        const float yv = ynext;
-        ynext = w.yp[s + 1];
-        float ds = diag_s, dc = diag_c, us = up_s, uc = up_c;
-        const int off = w.rbase - (s - lane);
+    xvec xr, x;
+    T A[H], Bv[H];
 #pragma unroll
-        for (int h = 0; h < H; ++h) {
-            float xe = x[h];
-            if constexpr (BANDED) xe = outside(off, h, w.band) ? kBig : xe;
-            const float d = xe - yv;
-            const float q = d * d;
-            const float p = min3f(ds, us, ss[h]);
-            const float csel = (p == ds) ? dc : ((p == us) ? uc : cc[h]);
-            const float yk = q - csel;
-            const float t = p + yk;
-            float cn = (t - p) - yk;
-            cn = (t < kInf) ? cn : 0.0f;
-            ds = ss[h];
-            dc = cc[h];
-            ss[h] = t;
-            cc[h] = cn;
-            us = t;
-            uc = cn;
-        }
-        const float rs = lane_shift_down(ss[H - 1], kInf);
-        const float rc = lane_shift_down(cc[H - 1], 0.0f);
-        diag_s = up_s;
-        diag_c = up_c;
-        up_s = rs;
-        up_c = rc;
+    for (int h = 0; h < H; ++h) {
+        const int r = rbase + h;
+        xr[h] = xa[h];
+        x[h] = (!EVENTS || (r < n && r - band <= 0)) ? xa[h] : kBig;
+        A[h] = ACC::inf();
+        Bv[h] = ACC::inf();
     }
-    float rs = pick<H>(ss, w.hstar), rc = pick<H>(cc, w.hstar);
-    const float res = (rs < kInf) ? rs - rc : rs;
-    if (lane == w.lstar) *w.out_at = res;
+    BandEvents ev;
+    if constexpr (EVENTS) ev.init<H>(band, n, wave, D);
+    if constexpr (G > 1) {
+        for (int k = threadIdx.x; k < (G - 1) * kRing; k += 64 * G) ring[k / kRing][k % kRing] = ACC::inf();
+        __syncthreads();
+    }
+    T up_in = ACC::inf();
+    T diag_in = (lane == 0 && wave == 0) ? ACC::zero() : ACC::inf();  // c(0,0) of the 1-based recurrence
+
+    // y of column s - skew; the +inf pads cover the columns a single wavefront
+    // reads ([-63, m+64]), later wavefronts clamp into [-1, m]
+    auto yat = [&](int s) {
+        const int c = s - skew;
+        if constexpr (G == 1) return yp[c];
+        return yp[c < -1 ? -1 : (c > m ? m : c)];
+    };
+    // value handed to lane 0 of this wavefront (LDS ring for wavefronts after the first)
+    auto boundary = [&](int s) -> T {
+        if constexpr (G > 1) {
+            if (wave > 0) return ring[wave - 1][(s - skew) & (kRing - 1)];
+        }
+        return ACC::inf();
+    };
+    auto publish = [&](int s, const T &bottom) {
+        if constexpr (G > 1) {
+            if (lane == 63 && wave < G - 1) ring[wave][(s - skew) & (kRing - 1)] = bottom;
+        }
+    };
+
+    // Every wavefront of the workgroup runs steps 0..sfinal (a uniform count,
+    // so all reach the same barriers); the result is read after the last step.
+    float y0 = yat(0), y1 = yat(1);
+    int s = 0;
+    for (; s + 2 <= sfinal + 1; s += 2) {
+        const float y2 = yat(s + 2), y3 = yat(s + 3);
+        if constexpr (EVENTS) ev.step<H>(s, x, xr, lane);
+        strip_step<ACC, H, PERCELL>(s - skew, y0, x, A, Bv, up_in, diag_in, rbase, band);
+        {
+            const T recv = lane_shift_down(Bv[H - 1], boundary(s + 1));
+            publish(s, Bv[H - 1]);
+            diag_in = up_in;
+            up_in = recv;
+        }
+        if constexpr (EVENTS) ev.step<H>(s + 1, x, xr, lane);
+        strip_step<ACC, H, PERCELL>(s + 1 - skew, y1, x, Bv, A, up_in, diag_in, rbase, band);
+        {
+            const T recv = lane_shift_down(A[H - 1], boundary(s + 2));
+            publish(s + 1, A[H - 1]);
+            diag_in = up_in;
+            up_in = recv;
+        }
+        y0 = y2;
+        y1 = y3;
+        if constexpr (G > 1) {
+            if ((s + 2) % kEpoch == 0) __syncthreads();
+        }
+    }
+    T res;
+    if (s <= sfinal) {  // one step left (s == sfinal)
+        if constexpr (EVENTS) ev.step<H>(s, x, xr, lane);
+        strip_step<ACC, H, PERCELL>(s - skew, y0, x, A, Bv, up_in, diag_in, rbase, band);
+        res = pick<H>(Bv, hf);
+    } else {
+        res = pick<H>(A, hf);
+    }
+    if (wave == wf && lane == lf) {
+        const int a = it.rows < it.cols ? it.rows : it.cols;
+        const int b = it.rows < it.cols ? it.cols : it.rows;
+        DI.out[condensed_index(a, b, DI.N)] = ACC::result(res);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -517,20 +522,45 @@ constexpr std::array<LaneFn, sizeof...(I)> make_lane_table(std::index_sequence<I
 const std::array<LaneFn, (kLaneMaxW + 1) / 2> kLaneTable =
     make_lane_table(std::make_index_sequence<(kLaneMaxW + 1) / 2>{});
 
-template <int H, bool BANDED>
-hipError_t wave_launch_h(int accum, const float *ws, const SeriesInfo *ser, const DatasetInfo *dsi,
-                         const WaveItem *items, int64_t n, hipStream_t st) {
-    const dim3 grid(static_cast<unsigned>(n)), block(64);
-    switch (accum) {
-        case 0: hipLaunchKernelGGL((k_wave_plain<H, BANDED>), grid, block, 0, st, ws, ser, dsi, items); break;
-        case 1: hipLaunchKernelGGL((k_wave_kahan<H, BANDED>), grid, block, 0, st, ws, ser, dsi, items); break;
-        case 2: hipLaunchKernelGGL((k_wave_fp64<H, BANDED>), grid, block, 0, st, ws, ser, dsi, items); break;
-        default: return hipErrorInvalidValue;
-    }
+template <class ACC, int H, int G>
+hipError_t strip_launch(bool banded, const float *ws, const SeriesInfo *ser, const DatasetInfo *dsi,
+                        const WaveItem *items, int64_t n, hipStream_t st) {
+    const dim3 grid(static_cast<unsigned>(n)), block(64 * G);
+    if (banded)
+        hipLaunchKernelGGL((k_strip<ACC, H, G, true>), grid, block, 0, st, ws, ser, dsi, items);
+    else
+        hipLaunchKernelGGL((k_strip<ACC, H, G, false>), grid, block, 0, st, ws, ser, dsi, items);
     return hipGetLastError();
 }
 
-constexpr int kWaveH[] = {1, 2, 4, 8, 12, 16, 24, 32, 48, 64};
+using StripFn = hipError_t (*)(bool, const float *, const SeriesInfo *, const DatasetInfo *, const WaveItem *,
+                               int64_t, hipStream_t);
+struct StripEntry {
+    int accum, H, G;
+    StripFn fn;
+};
+
+// Instantiated shapes, per accumulation mode in increasing row capacity 64*H*G.
+const StripEntry kStrips[] = {
+    {0, 1, 1, &strip_launch<AccPlain, 1, 1>},   {0, 2, 1, &strip_launch<AccPlain, 2, 1>},
+    {0, 4, 1, &strip_launch<AccPlain, 4, 1>},   {0, 8, 1, &strip_launch<AccPlain, 8, 1>},
+    {0, 12, 1, &strip_launch<AccPlain, 12, 1>}, {0, 16, 1, &strip_launch<AccPlain, 16, 1>},
+    {0, 24, 1, &strip_launch<AccPlain, 24, 1>}, {0, 32, 1, &strip_launch<AccPlain, 32, 1>},
+    {0, 16, 2, &strip_launch<AccPlain, 16, 2>}, {0, 48, 1, &strip_launch<AccPlain, 48, 1>},
+    {0, 24, 2, &strip_launch<AccPlain, 24, 2>}, {0, 64, 1, &strip_launch<AccPlain, 64, 1>},
+    {0, 32, 2, &strip_launch<AccPlain, 32, 2>}, {0, 32, 4, &strip_launch<AccPlain, 32, 4>},
+    {0, 32, 8, &strip_launch<AccPlain, 32, 8>}, {0, 64, 8, &strip_launch<AccPlain, 64, 8>},
+    {1, 1, 1, &strip_launch<AccKahan, 1, 1>},   {1, 2, 1, &strip_launch<AccKahan, 2, 1>},
+    {1, 4, 1, &strip_launch<AccKahan, 4, 1>},   {1, 8, 1, &strip_launch<AccKahan, 8, 1>},
+    {1, 16, 1, &strip_launch<AccKahan, 16, 1>}, {1, 16, 2, &strip_launch<AccKahan, 16, 2>},
+    {1, 16, 4, &strip_launch<AccKahan, 16, 4>}, {1, 16, 8, &strip_launch<AccKahan, 16, 8>},
+    {1, 16, 16, &strip_launch<AccKahan, 16, 16>},
+    {2, 1, 1, &strip_launch<AccF64, 1, 1>},     {2, 2, 1, &strip_launch<AccF64, 2, 1>},
+    {2, 4, 1, &strip_launch<AccF64, 4, 1>},     {2, 8, 1, &strip_launch<AccF64, 8, 1>},
+    {2, 16, 1, &strip_launch<AccF64, 16, 1>},   {2, 16, 2, &strip_launch<AccF64, 16, 2>},
+    {2, 16, 4, &strip_launch<AccF64, 16, 4>},   {2, 16, 8, &strip_launch<AccF64, 16, 8>},
+    {2, 16, 16, &strip_launch<AccF64, 16, 16>},
+};
 
 }  // namespace
 
@@ -550,33 +580,23 @@ hipError_t launch_lane(int W, const float *ws, const SeriesInfo *ser, const Data
     return kLaneTable[(W - 1) / 2](ws, ser, dsi, items, n_items, stream);
 }
 
-int wave_rows_per_lane(int n) {
-    for (int H : kWaveH)
-        if (64 * H >= n) return H;
-    return 0;
+int strip_shapes(int accum, StripShape *out, int max_out) {
+    int k = 0;
+    for (const StripEntry &e : kStrips)
+        if (e.accum == accum) {
+            if (out && k < max_out) out[k] = StripShape{e.H, e.G};
+            ++k;
+        }
+    return k;
 }
 
-hipError_t launch_wave(int H, bool banded, int accum, const float *ws, const SeriesInfo *ser,
-                       const DatasetInfo *dsi, const WaveItem *items, int64_t n_items, hipStream_t stream) {
+hipError_t launch_strip(int accum, StripShape shape, bool banded, const float *ws, const SeriesInfo *ser,
+                        const DatasetInfo *dsi, const WaveItem *items, int64_t n_items, hipStream_t stream) {
     if (n_items <= 0) return hipSuccess;
-#define DTWMI_WAVE_CASE(HV)                                                                  \
-    case HV:                                                                                 \
-        return banded ? wave_launch_h<HV, true>(accum, ws, ser, dsi, items, n_items, stream) \
-                      : wave_launch_h<HV, false>(accum, ws, ser, dsi, items, n_items, stream);
-    switch (H) {
-        DTWMI_WAVE_CASE(1)
-        DTWMI_WAVE_CASE(2)
-        DTWMI_WAVE_CASE(4)
-        DTWMI_WAVE_CASE(8)
-        DTWMI_WAVE_CASE(12)
-        DTWMI_WAVE_CASE(16)
-        DTWMI_WAVE_CASE(24)
-        DTWMI_WAVE_CASE(32)
-        DTWMI_WAVE_CASE(48)
-        DTWMI_WAVE_CASE(64)
-        default: return hipErrorInvalidValue;
-    }
-#undef DTWMI_WAVE_CASE
+    for (const StripEntry &e : kStrips)
+        if (e.accum == accum && e.H == shape.H && e.G == shape.G)
+            return e.fn(banded, ws, ser, dsi, items, n_items, stream);
+    return hipErrorInvalidValue;
 }
 
 }  // namespace dtwmi

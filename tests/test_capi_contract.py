@@ -99,9 +99,11 @@ def test_unsupported_requests_rejected_on_host():
     assert rc == B.DTW_ERR_UNSUPPORTED and "lane-band" in msg
     # lane-band kernel with Kahan accumulation
     assert _call_ex([4, 4], [0, 4], kernel=1, accum=1)[0] == B.DTW_ERR_UNSUPPORTED
-    # both series of a pair longer than the wavefront kernel covers
-    rc, msg = _call_ex([5000, 5000], [0, 5000])
-    assert rc == B.DTW_ERR_UNSUPPORTED and "4096" in msg
+    # both series of a pair longer than the wavefront kernels cover
+    rc, msg = _call_ex([40000, 40000], [0, 40000])
+    assert rc == B.DTW_ERR_UNSUPPORTED and "32768" in msg
+    rc, msg = _call_ex([20000, 20000], [0, 20000], accum=1)
+    assert rc == B.DTW_ERR_UNSUPPORTED and "16384" in msg
 
 
 def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):

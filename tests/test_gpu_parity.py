@@ -17,6 +17,7 @@ pytestmark = pytest.mark.gpu
 
 REL_TOL = 1e-5
 REL_TOL_16BIT_PLAIN = 1e-3
+REL_TOL_LONG_PLAIN = 1e-4  # plain FP32 sums on series longer than 4096 points
 
 
 def _gpu():
@@ -127,6 +128,38 @@ def test_long_strips_and_unequal_lengths():
         got = run(ds)
         pi, pj = oracle.all_pairs_list(ds.N)
         assert_close(got, oracle_pairs(ds, pi, pj), what="long w=%d" % w)
+
+
+@pytest.mark.parametrize("accum", ["plain", "kahan", "fp64"])
+def test_series_longer_than_one_wavefront(accum):
+    # shorter series of 4097..9000 points: strips spread over 2..8 wavefronts of a workgroup
+    rng = np.random.default_rng(17)
+    lens = [4097, 5000, 9000, 7000] if accum == "plain" else [4097, 5200, 3000]
+    series = [synth.random_walk(rng, L) for L in lens]
+    for w in (-1, 700):
+        ds = synth.pack(series, "long%s" % accum, w)
+        got = run(ds, accum=accum)
+        pi, pj = oracle.all_pairs_list(ds.N)
+        ref = oracle_pairs(ds, pi, pj)
+        if accum == "fp64":
+            assert np.array_equal(got, ref.astype(np.float32))
+        else:
+            # plain FP32 sums over paths of up to 16,000 cells drift past 1e-5 (each add rounds;
+            # relative error bound (k-1)*2^-24); the compensated sums keep 1e-5
+            assert_close(got, ref, tol=REL_TOL_LONG_PLAIN if accum == "plain" else REL_TOL,
+                         what="long %s w=%d" % (accum, w))
+
+
+@pytest.mark.parametrize("accum", ["kahan", "fp64"])
+def test_precision_modes_ragged_windows(accum):
+    ds = synth.small_random(seed=61, N=25, len_lo=1, len_hi=1100, window=37)
+    got = run(ds, accum=accum)
+    pi, pj = oracle.all_pairs_list(ds.N)
+    ref = oracle_pairs(ds, pi, pj)
+    if accum == "fp64":
+        assert np.array_equal(got, ref.astype(np.float32))
+    else:
+        assert_close(got, ref, what="ragged %s" % accum)
 
 
 def test_single_point_series_and_two_series():
