@@ -25,12 +25,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# MI355X: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz.  FP32 vector peak 157.3
-# TFLOP/s counts a packed FMA as 2 lanes x 2 flops; as VALU lane-operations
-# (one FMA, min3 or sub = 1 op) that is 78.64 T op/s with packed issue and
-# 39.32 T op/s with one unpacked VALU instruction per SIMD every 4 cycles.
+# MI355X: 256 CUs at 2.4 GHz.  The published FP32 vector peak of 157.3 TFLOP/s
+# is 256 CU x 128 lanes x 2 flops (FMA) x 2.4 GHz; counted as VALU
+# lane-operations (one FMA, min3 or sub = 1 op) it is 78.64 T op/s.
 PEAK_LANE_OPS_T = 256 * 128 * 2.4e9 / 1e12          # 78.64
-PEAK_UNPACKED_LANE_OPS_T = 256 * 64 * 2.4e9 / 1e12  # 39.32
 OPS_PER_CELL = 3
 # profile summary (profiles/<label>*.md) holding the counter-based HBM traffic of a workload's DP kernel
 PROFILE_LABELS = {("c2", "auto", "plain", "f32"): "lane_band_W103_c2"}
@@ -145,7 +143,7 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
-    ap.add_argument("--kernel", default="auto", choices=["auto", "lane", "wave"])
+    ap.add_argument("--kernel", default="auto", choices=["auto", "lane", "wave", "cyclic"])
     ap.add_argument("--accum", default="plain", choices=["plain", "kahan", "fp64"])
     ap.add_argument("--dtype", default="f32", choices=["f32", "bf16", "f16"],
                     help="storage type of the series (the long-series workload's precision study)")
@@ -234,7 +232,6 @@ def main(argv=None):
             "peak": round(PEAK_LANE_OPS_T, 2),
             "unit": "TOP/s (FP32 VALU lane-ops)",
             "frac": round(achieved / PEAK_LANE_OPS_T, 4),
-            "frac_of_unpacked_issue": round(achieved / PEAK_UNPACKED_LANE_OPS_T, 4),
             "kernel_ms": round(k_avg, 4),
             "ops_per_launch": OPS_PER_CELL * cells,
             "traffic": recorded_traffic(PROFILE_LABELS.get((args.workload, args.kernel, args.accum, args.dtype), "-")),

@@ -56,13 +56,18 @@ typedef enum { DTW_F32 = 0, DTW_BF16 = 1, DTW_F16 = 2 } dtw_dtype;
  *   FP64:  the whole recurrence in FP64, the final cost rounded once to FP32. */
 typedef enum { DTW_ACC_PLAIN = 0, DTW_ACC_KAHAN = 1, DTW_ACC_FP64 = 2 } dtw_accum;
 
-/* Kernel family; AUTO picks per dataset.  The others exist for tests/benches.
- *   LANE: one pair per lane, the band row kept in registers (all series of the
- *         dataset of equal length, 2*w+1 <= 127, PLAIN only).
- *   WAVE: one pair per workgroup of 1..16 wavefronts sweeping anti-diagonals,
- *         each lane owning a strip of rows (any lengths, any window, any
- *         accumulation). */
-typedef enum { DTW_KERNEL_AUTO = 0, DTW_KERNEL_LANE = 1, DTW_KERNEL_WAVE = 2 } dtw_kernel;
+/* Kernel family; AUTO picks per dataset and per pair.  The others exist for
+ * tests and benchmarks.
+ *   LANE:   one pair per lane, the band row kept in registers (all series of
+ *           the dataset of equal length, 2*w+1 <= 127, PLAIN only).
+ *   WAVE:   one pair per workgroup of 1..16 wavefronts sweeping anti-diagonals,
+ *           each lane owning a strip of rows (any lengths, any window, any
+ *           accumulation).
+ *   CYCLIC: one pair per wavefront; blocks of rows of the longer series cycle
+ *           over the 64 lanes and each block only visits the columns its window
+ *           admits (PLAIN only).  Pairs without a window, or whose window is too
+ *           wide for any instantiated block height, use WAVE. */
+typedef enum { DTW_KERNEL_AUTO = 0, DTW_KERNEL_LANE = 1, DTW_KERNEL_WAVE = 2, DTW_KERNEL_CYCLIC = 3 } dtw_kernel;
 
 /* One dataset: N series concatenated in one device buffer. */
 typedef struct dtw_dataset {
@@ -79,6 +84,9 @@ typedef struct dtw_options {
     int32_t accum;  /* dtw_accum */
     int32_t kernel; /* dtw_kernel (0 = AUTO) */
     int32_t flags;  /* bit 0: record HIP events around the DP kernels (plan API only) */
+    int32_t rows_per_lane; /* 0 = automatic.  Else the rows each lane holds in the WAVE and
+                              CYCLIC kernels (1..64); a value with no instantiated kernel for a
+                              pair returns DTW_ERR_UNSUPPORTED.  Ignored by LANE. */
     void *stream;   /* hipStream_t used by dtw_pairwise_ex; NULL = default stream */
 } dtw_options;
 
@@ -94,7 +102,8 @@ typedef struct dtw_plan_stats {
     int64_t workspace_bytes; /* device memory owned by the plan */
     int32_t n_launches;      /* kernel launches per execute, staging included */
     int32_t n_lane_items;    /* LANE work items (64 pairs each) */
-    int64_t n_wave_items;    /* WAVE work items (one pair each) */
+    int64_t n_wave_items;    /* WAVE and CYCLIC work items (one pair each) */
+    int64_t n_cyclic_items;  /* the CYCLIC ones among them */
 } dtw_plan_stats;
 
 /*

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_build", "l
 DTW_OK, DTW_ERR_INVALID_ARG, DTW_ERR_UNSUPPORTED, DTW_ERR_OUT_OF_MEMORY, DTW_ERR_HIP = range(5)
 DTYPES = {"f32": 0, "bf16": 1, "f16": 2}
 ACCUM = {"plain": 0, "kahan": 1, "fp64": 2}
-KERNELS = {"auto": 0, "lane": 1, "wave": 2}
+KERNELS = {"auto": 0, "lane": 1, "wave": 2, "cyclic": 3}
 DTW_FLAG_TIMING = 1
 
 EXPORTED = ["dtw_pairwise", "dtw_pairwise_ex", "dtw_plan_create", "dtw_plan_execute",
@@ -39,13 +39,14 @@ class dtw_dataset(ctypes.Structure):
 
 class dtw_options(ctypes.Structure):
     _fields_ = [("dtype", ctypes.c_int32), ("accum", ctypes.c_int32), ("kernel", ctypes.c_int32),
-                ("flags", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+                ("flags", ctypes.c_int32), ("rows_per_lane", ctypes.c_int32), ("stream", ctypes.c_void_p)]
 
 
 class dtw_plan_stats(ctypes.Structure):
     _fields_ = [("pairs", ctypes.c_int64), ("band_cells", ctypes.c_int64), ("computed_cells", ctypes.c_int64),
                 ("workspace_bytes", ctypes.c_int64), ("n_launches", ctypes.c_int32),
-                ("n_lane_items", ctypes.c_int32), ("n_wave_items", ctypes.c_int64)]
+                ("n_lane_items", ctypes.c_int32), ("n_wave_items", ctypes.c_int64),
+                ("n_cyclic_items", ctypes.c_int64)]
 
 
 _lib = None
@@ -126,12 +127,13 @@ def _make_dataset(series, lengths, offsets, window, out):
     return d, (ln, off)
 
 
-def _options(dtype="f32", accum="plain", kernel="auto", flags=0, stream=None):
+def _options(dtype="f32", accum="plain", kernel="auto", flags=0, stream=None, rows_per_lane=0):
     o = dtw_options()
     o.dtype = DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
     o.accum = ACCUM[accum] if isinstance(accum, str) else int(accum)
     o.kernel = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
     o.flags = int(flags)
+    o.rows_per_lane = int(rows_per_lane)
     o.stream = _stream_handle(stream) if stream is not False else ctypes.c_void_p(0)
     return o
 
@@ -145,10 +147,10 @@ def dtw_pairwise(series, lengths, offsets, N, window, out_condensed):
 
 
 def dtw_pairwise_ex(series, lengths, offsets, window, out_condensed, dtype="f32", accum="plain", kernel="auto",
-                    stream=None):
+                    stream=None, rows_per_lane=0):
     """One dataset with options (blocking).  `series` holds f32, bf16 (as int16/uint16 bits) or f16 values."""
     d, keep = _make_dataset(series, lengths, offsets, window, out_condensed)
-    o = _options(dtype, accum, kernel, 0, stream)
+    o = _options(dtype, accum, kernel, 0, stream, rows_per_lane)
     _check(load().dtw_pairwise_ex(ctypes.byref(d), ctypes.byref(o)))
     del keep
 
@@ -160,7 +162,7 @@ class Plan:
     The tensors must stay alive, at the same address, while the plan exists.
     """
 
-    def __init__(self, datasets, dtype="f32", accum="plain", kernel="auto", timing=False):
+    def __init__(self, datasets, dtype="f32", accum="plain", kernel="auto", timing=False, rows_per_lane=0):
         self._lib = load()
         arr = (dtw_dataset * max(1, len(datasets)))()
         self._keep = []
@@ -168,7 +170,7 @@ class Plan:
             d, keep = _make_dataset(series, lengths, offsets, window, out)
             arr[k] = d
             self._keep.append((keep, series, out))
-        o = _options(dtype, accum, kernel, DTW_FLAG_TIMING if timing else 0, False)
+        o = _options(dtype, accum, kernel, DTW_FLAG_TIMING if timing else 0, False, rows_per_lane)
         self._h = ctypes.c_void_p()
         _check(self._lib.dtw_plan_create(ctypes.byref(self._h), arr, len(datasets), ctypes.byref(o)))
 
@@ -210,11 +212,12 @@ def device_series(ds, device="cuda"):
     return t.to(device)
 
 
-def pairwise(ds, accum="plain", kernel="auto", device="cuda", out=None):
+def pairwise(ds, accum="plain", kernel="auto", device="cuda", out=None, rows_per_lane=0):
     """Condensed DTW matrix of a synth.Dataset on the GPU, returned as a torch tensor (blocking)."""
     import torch
     series = device_series(ds, device)
     if out is None:
         out = torch.full((max(0, ds.n_pairs),), float("nan"), dtype=torch.float32, device=device)
-    dtw_pairwise_ex(series, ds.lengths, ds.offsets, ds.window, out, dtype=ds.dtype, accum=accum, kernel=kernel)
+    dtw_pairwise_ex(series, ds.lengths, ds.offsets, ds.window, out, dtype=ds.dtype, accum=accum, kernel=kernel,
+                    rows_per_lane=rows_per_lane)
     return out

@@ -10,9 +10,13 @@
 //    a < N/2 when N is even.  Every unordered pair appears exactly once and
 //    every series gets the same number of partners, so the 64-pair work items
 //    are almost all full.
-//  * wavefront datasets: one item per pair (i<j); the shorter series is the
-//    one spread over the lanes.  Items are grouped by kernel instance and each
-//    group is sorted by decreasing cell count, so the longest pairs start first.
+//  * wavefront datasets: one item per pair (i<j).  Each pair goes either to a
+//    strip kernel (the shorter series spread over the lanes, every column
+//    swept) or, with PLAIN accumulation and a window, to the cyclic kernel
+//    (blocks of the longer series cycling over the lanes, each block visiting
+//    only its window), whichever a step-count cost model finds cheaper.
+//    Items are grouped by kernel instance and each group is sorted by
+//    decreasing cost, so the longest pairs start first.
 #include "dtw_internal.h"
 #include "dtwmi.h"
 
@@ -78,19 +82,71 @@ struct LaneGroup {
 };
 
 struct WaveGroup {
-    StripShape shape;
+    StripShape shape;  // G == 0: cyclic kernel with H = shape.H
     bool banded;
     int64_t begin, count;
 };
 
 // Strip shape for a pair whose shorter series has n points: the instantiated
-// shape of smallest row capacity 64*H*G >= n ({0,0} if none is large enough).
-StripShape pick_strip(int accum, int n) {
+// shape of smallest row capacity 64*H*G >= n, restricted to H == force_h when
+// force_h > 0 ({0,0} if none fits).
+StripShape pick_strip(int accum, int n, int force_h) {
     StripShape shapes[64];
     const int k = strip_shapes(accum, shapes, 64);
     for (int i = 0; i < k && i < 64; ++i)
-        if (64 * shapes[i].H * shapes[i].G >= n) return shapes[i];
+        if (64 * shapes[i].H * shapes[i].G >= n && (force_h <= 0 || shapes[i].H == force_h)) return shapes[i];
     return StripShape{0, 0};
+}
+
+// Cost model shared by both wavefront families: wavefront-steps times VALU
+// instructions per step (3 per cell row plus loop overhead per step), from
+// the instruction mix of the compiled loops.
+constexpr int64_t kStripStepOverhead = 15;
+constexpr int64_t kCyclicStepOverhead = 20;
+
+// Steps a strip workgroup takes on an n x m pair (n = rows spread over lanes).
+int64_t strip_steps(StripShape sh, int64_t n, int64_t m) {
+    const int64_t lanes = (n - 1) / sh.H;  // last lane holding a row
+    return m + lanes % 64 + (lanes / 64) * (64 + (sh.G > 1 ? 16 : 0));
+}
+
+int64_t strip_cost(StripShape sh, int64_t n, int64_t m) {
+    return sh.G * strip_steps(sh, n, m) * (3 * sh.H + kStripStepOverhead);
+}
+
+// Cyclic kernel, rows = the longer series (n points), cols = the shorter (m),
+// band b >= 0.  Blocks of H rows; block q sweeps columns at steps q + c.  A
+// lane may take block q+64 only after block q has left its window, which holds
+// when there are at most 64 blocks or 64(H+1) >= 2b+H.
+bool cyclic_fits(int H, int64_t n, int64_t b) {
+    const int64_t Q = (n + H - 1) / H;
+    return Q <= 64 || 64 * (int64_t)(H + 1) >= 2 * b + H;
+}
+
+int64_t cyclic_steps(int H, int64_t n, int64_t m) { return m + (n - 1) / H; }
+
+int64_t cyclic_cost(int H, int64_t n, int64_t m) {
+    return cyclic_steps(H, n, m) * (3 * H + kCyclicStepOverhead);
+}
+
+// Cheapest instantiated cyclic block height for the pair (0 if none fits);
+// force_h > 0 restricts the choice to that height.
+int pick_cyclic(int64_t n, int64_t m, int64_t b, int force_h, int64_t *cost) {
+    int hs[32];
+    const int k = cyclic_shapes(hs, 32);
+    int best = 0;
+    int64_t best_cost = 0;
+    for (int i = 0; i < k && i < 32; ++i) {
+        const int H = hs[i];
+        if ((force_h > 0 && H != force_h) || !cyclic_fits(H, n, b)) continue;
+        const int64_t c = cyclic_cost(H, n, m);
+        if (!best || c < best_cost) {
+            best = H;
+            best_cost = c;
+        }
+    }
+    *cost = best_cost;
+    return best;
 }
 
 int max_strip_rows(int accum) {
@@ -129,8 +185,12 @@ int validate_options(const dtw_options *opt) {
     if (opt->dtype < DTW_F32 || opt->dtype > DTW_F16) return fail(DTW_ERR_INVALID_ARG, "unknown dtype %d", opt->dtype);
     if (opt->accum < DTW_ACC_PLAIN || opt->accum > DTW_ACC_FP64)
         return fail(DTW_ERR_INVALID_ARG, "unknown accumulation mode %d", opt->accum);
-    if (opt->kernel < DTW_KERNEL_AUTO || opt->kernel > DTW_KERNEL_WAVE)
+    if (opt->kernel < DTW_KERNEL_AUTO || opt->kernel > DTW_KERNEL_CYCLIC)
         return fail(DTW_ERR_INVALID_ARG, "unknown kernel family %d", opt->kernel);
+    if (opt->rows_per_lane < 0 || opt->rows_per_lane > 64)
+        return fail(DTW_ERR_INVALID_ARG, "rows_per_lane=%d outside 0..64", opt->rows_per_lane);
+    if (opt->kernel == DTW_KERNEL_CYCLIC && opt->accum != DTW_ACC_PLAIN)
+        return fail(DTW_ERR_UNSUPPORTED, "the cyclic kernel needs PLAIN accumulation");
     if (opt->flags & ~DTW_FLAG_TIMING) return fail(DTW_ERR_INVALID_ARG, "unknown flags 0x%x", opt->flags);
     return DTW_OK;
 }
@@ -188,6 +248,7 @@ int dtw_plan_create(dtw_plan *plan_out, const dtw_dataset *ds, int32_t n_dataset
     const int accum = opt ? opt->accum : DTW_ACC_PLAIN;
     const int kernel = opt ? opt->kernel : DTW_KERNEL_AUTO;
     const int flags = opt ? opt->flags : 0;
+    const int force_h = opt ? opt->rows_per_lane : 0;
 
     // ---- host-side planning (no HIP calls) ----
     std::vector<SeriesSrc> src;
@@ -195,7 +256,8 @@ int dtw_plan_create(dtw_plan *plan_out, const dtw_dataset *ds, int32_t n_dataset
     std::vector<DatasetInfo> dsi;
     std::vector<LaneItem> lane_items;
     std::map<int, std::vector<LaneItem>> lane_by_w;
-    std::map<std::pair<int, bool>, std::vector<std::pair<int64_t, WaveItem>>> wave_by_kind;
+    // wave items by kernel instance (H, G, banded); G == 0 is the cyclic kernel
+    std::map<std::tuple<int, int, bool>, std::vector<std::pair<int64_t, WaveItem>>> wave_by_kind;
     dtw_plan_stats st{};
     size_t ws_floats = 0;
     const size_t elem = dtype == DTW_F32 ? 4 : 2;
@@ -240,7 +302,7 @@ int dtw_plan_create(dtw_plan *plan_out, const dtw_dataset *ds, int32_t n_dataset
             return fail(DTW_ERR_UNSUPPORTED,
                         "dataset %d: the lane-band kernel needs equal lengths, PLAIN accumulation and 2*w+1 <= %d",
                         d, kLaneMaxW);
-        if (kernel == DTW_KERNEL_WAVE) lane_w = 0;
+        if (kernel == DTW_KERNEL_WAVE || kernel == DTW_KERNEL_CYCLIC) lane_w = 0;
 
         if (lane_w) {
             const int32_t N = D.N, L = D.lengths[0], b = (lane_w - 1) / 2;
@@ -259,20 +321,39 @@ int dtw_plan_create(dtw_plan *plan_out, const dtw_dataset *ds, int32_t n_dataset
                 for (int32_t j = i + 1; j < D.N; ++j) {
                     const int32_t ni = D.lengths[i], nj = D.lengths[j];
                     const bool swap = nj < ni;
-                    const int32_t rows = swap ? j : i, cols = swap ? i : j;
+                    const int32_t shorter = swap ? j : i, longer = swap ? i : j;
                     const int32_t n = std::min(ni, nj), m = std::max(ni, nj);
-                    const StripShape sh = pick_strip(accum, n);
-                    if (!sh.H)
-                        return fail(DTW_ERR_UNSUPPORTED,
-                                    "dataset %d: pair (%d,%d) has both series longer than %d points", d, i, j,
-                                    max_strip_rows(accum));
                     const int64_t b = effective_band(D.window, n, m);
                     const int64_t cells = band_cells(n, m, b);
                     st.band_cells += cells;
-                    const int64_t lanes = (n - 1) / sh.H;  // last lane holding a row
-                    st.computed_cells += (int64_t)64 * sh.G * sh.H *
-                                         (m + lanes % 64 + (lanes / 64) * (64 + (sh.G > 1 ? 16 : 0)));
-                    wave_by_kind[{sh.H * 1000 + sh.G, b >= 0}].push_back({cells, WaveItem{d, rows, cols, (int32_t)b}});
+                    // cyclic candidate: PLAIN, a window, rows = the longer series
+                    int64_t cyc_cost = 0;
+                    const int cyc_h = (accum == DTW_ACC_PLAIN && b >= 0 && kernel != DTW_KERNEL_WAVE)
+                                          ? pick_cyclic(m, n, b, force_h, &cyc_cost)
+                                          : 0;
+                    const StripShape sh = kernel == DTW_KERNEL_CYCLIC && cyc_h ? StripShape{0, 0}
+                                                                               : pick_strip(accum, n, force_h);
+                    if (!sh.H && !cyc_h) {
+                        if (force_h > 0)
+                            return fail(DTW_ERR_UNSUPPORTED,
+                                        "dataset %d: pair (%d,%d) (%d x %d points, band %lld): no kernel with "
+                                        "rows_per_lane=%d fits it",
+                                        d, i, j, n, m, (long long)b, force_h);
+                        return fail(DTW_ERR_UNSUPPORTED,
+                                    "dataset %d: pair (%d,%d) has both series longer than %d points", d, i, j,
+                                    max_strip_rows(accum));
+                    }
+                    const int64_t s_cost = sh.H ? strip_cost(sh, n, m) : 0;
+                    if (cyc_h && (!sh.H || cyc_cost < s_cost)) {
+                        st.computed_cells += (int64_t)64 * cyc_h * cyclic_steps(cyc_h, m, n);
+                        ++st.n_cyclic_items;
+                        wave_by_kind[std::make_tuple(cyc_h, 0, true)].push_back(
+                            {cyc_cost, WaveItem{d, longer, shorter, (int32_t)b}});
+                    } else {
+                        st.computed_cells += (int64_t)64 * sh.G * sh.H * strip_steps(sh, n, m);
+                        wave_by_kind[std::make_tuple(sh.H, sh.G, b >= 0)].push_back(
+                            {s_cost, WaveItem{d, shorter, longer, (int32_t)b}});
+                    }
                 }
             }
         }
@@ -291,18 +372,22 @@ int dtw_plan_create(dtw_plan *plan_out, const dtw_dataset *ds, int32_t n_dataset
         p->lane_groups.push_back(LaneGroup{kv.first, (int64_t)lane_items.size(), (int64_t)kv.second.size()});
         lane_items.insert(lane_items.end(), kv.second.begin(), kv.second.end());
     }
-    // Larger strips first (by row capacity); inside a group, larger pairs first.
-    std::vector<std::map<std::pair<int, bool>, std::vector<std::pair<int64_t, WaveItem>>>::iterator> order;
-    for (auto it = wave_by_kind.begin(); it != wave_by_kind.end(); ++it) order.push_back(it);
-    std::stable_sort(order.begin(), order.end(), [](const auto &a, const auto &b) {
-        return (a->first.first / 1000) * (a->first.first % 1000) > (b->first.first / 1000) * (b->first.first % 1000);
-    });
+    // Inside a group, costlier pairs first; groups in decreasing order of their
+    // costliest pair.
+    std::vector<decltype(wave_by_kind)::iterator> order;
+    for (auto it = wave_by_kind.begin(); it != wave_by_kind.end(); ++it) {
+        std::stable_sort(it->second.begin(), it->second.end(),
+                         [](const std::pair<int64_t, WaveItem> &a, const std::pair<int64_t, WaveItem> &b) {
+                             return a.first > b.first;
+                         });
+        order.push_back(it);
+    }
+    std::stable_sort(order.begin(), order.end(),
+                     [](const auto &a, const auto &b) { return a->second[0].first > b->second[0].first; });
     for (auto it : order) {
         auto &v = it->second;
-        std::stable_sort(v.begin(), v.end(), [](const std::pair<int64_t, WaveItem> &a,
-                                                const std::pair<int64_t, WaveItem> &b) { return a.first > b.first; });
-        const StripShape sh{it->first.first / 1000, it->first.first % 1000};
-        p->wave_groups.push_back(WaveGroup{sh, it->first.second, (int64_t)wave_items.size(), (int64_t)v.size()});
+        const StripShape sh{std::get<0>(it->first), std::get<1>(it->first)};
+        p->wave_groups.push_back(WaveGroup{sh, std::get<2>(it->first), (int64_t)wave_items.size(), (int64_t)v.size()});
         for (auto &e : v) wave_items.push_back(e.second);
     }
     st.n_lane_items = static_cast<int32_t>(lane_items.size());
@@ -383,7 +468,10 @@ int dtw_plan_execute(dtw_plan p, void *stream) {
         if (e != hipSuccess) return hip_fail(e, "lane-band kernel launch");
     }
     for (const WaveGroup &g : p->wave_groups) {
-        e = launch_strip(p->accum, g.shape, g.banded, p->ws, p->d_ser, p->d_ds, p->d_wave + g.begin, g.count, s);
+        if (g.shape.G == 0)
+            e = launch_cyclic(g.shape.H, p->ws, p->d_ser, p->d_ds, p->d_wave + g.begin, g.count, s);
+        else
+            e = launch_strip(p->accum, g.shape, g.banded, p->ws, p->d_ser, p->d_ds, p->d_wave + g.begin, g.count, s);
         if (e != hipSuccess) return hip_fail(e, "wavefront kernel launch");
     }
     if (p->ev1) {

@@ -65,5 +65,11 @@ struct StripShape {
 int strip_shapes(int accum, StripShape *out, int max_out);
 hipError_t launch_strip(int accum, StripShape shape, bool banded, const float *ws, const SeriesInfo *ser,
                         const DatasetInfo *dsi, const WaveItem *items, int64_t n_items, hipStream_t stream);
+// Cyclic banded strips (PLAIN, window required): H rows per block, blocks
+// cycling over the 64 lanes of one wavefront; needs 64(H+1) >= 2b+H whenever
+// the pair has more than 64 blocks.
+int cyclic_shapes(int *H_out, int max_out);
+hipError_t launch_cyclic(int H, const float *ws, const SeriesInfo *ser, const DatasetInfo *dsi,
+                         const WaveItem *items, int64_t n_items, hipStream_t stream);
 
 }  // namespace dtwmi

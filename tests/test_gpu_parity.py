@@ -17,7 +17,17 @@ pytestmark = pytest.mark.gpu
 
 REL_TOL = 1e-5
 REL_TOL_16BIT_PLAIN = 1e-3
-REL_TOL_LONG_PLAIN = 1e-4  # plain FP32 sums on series longer than 4096 points
+REL_TOL_LONG_PLAIN = 1e-4  # plain FP32 sums along warping paths of more than 4096 cells
+
+
+def plain_tol(ds):
+    """Tolerance of plain FP32 sums for a dataset: each add along a path of k
+    cells rounds once, so the relative error is about sqrt(k) * 2^-24 for
+    random rounding (bounded by (k-1) * 2^-24); 1e-5 holds up to paths of
+    4096 cells, longer paths get 1e-4 (the compensated modes keep 1e-5)."""
+    L = np.sort(np.asarray(ds.lengths, dtype=np.int64))
+    longest_path = int(L[-1] + L[-2] - 1) if L.size > 1 else 0
+    return REL_TOL if longest_path <= 4096 else REL_TOL_LONG_PLAIN
 
 
 def _gpu():
@@ -237,6 +247,117 @@ def test_long_series_precision_modes(dtype, accum):
         # 16-bit inputs with plain FP32 sums: 1e-3; FP32 inputs, or any input with compensated sums: 1e-5
         tol = REL_TOL_16BIT_PLAIN if (dtype != "f32" and accum == "plain") else REL_TOL
         assert_close(g, ref, tol=tol, what="500x4096 %s %s" % (dtype, accum))
+
+
+# ---------------------------------------------------------------- cyclic banded kernel
+
+CYCLIC_H = [1, 2, 4, 8, 12, 16, 24, 32]
+
+
+def _cyclic_band_limit(H):
+    # widest band b for which a lane can take block q+64 after block q: 64(H+1) >= 2b+H
+    return (64 * (H + 1) - H) // 2
+
+
+def _run_plan(ds, **kw):
+    plan, series, outs = _plan_for([ds], **kw)
+    plan.execute()
+    torch.cuda.synchronize()
+    info = plan.info()
+    got = outs[0].cpu().numpy()[:ds.n_pairs]
+    plan.destroy()
+    return got, info
+
+
+def band_edge_pairs(rng, lengths, b):
+    """Pairs (x, y) of equal length whose cheapest path runs along the band edge
+    i - j = b: x_i = y_max(0, i-b), so that path costs nothing."""
+    series = []
+    for n in lengths:
+        v = synth.random_walk(rng, int(n))
+        series.append(v[np.maximum(0, np.arange(n) - b)])
+        series.append(v)
+    return series
+
+
+@pytest.mark.parametrize("H", CYCLIC_H)
+def test_cyclic_kernel_each_block_height(H):
+    _gpu()
+    bmax = _cyclic_band_limit(H)
+    lo = 64 * H + 30  # more than 64 blocks of H rows: every lane takes several blocks
+    rng = np.random.default_rng(700 + H)
+    edge = band_edge_pairs(rng, [lo, lo + 7, lo + H + 1], bmax)
+    cases = [
+        # optimal paths along the band edge, band at the lane-reuse limit
+        synth.pack(edge, "edge%d" % H, bmax),
+        # band exactly at the lane-reuse limit (|n-m| <= bmax/2 <= w = bmax)
+        synth.small_random(seed=300 + H, N=8, len_lo=lo, len_hi=lo + bmax // 2, window=bmax),
+        # band well inside the limit, ragged last block
+        synth.small_random(seed=400 + H, N=8, len_lo=lo + 1, len_hi=lo + bmax // 3, window=bmax // 3),
+        # at most 64 blocks: any band width, lengths from 2 points up
+        synth.small_random(seed=500 + H, N=12, len_lo=2, len_hi=64 * H, window=3 * H + 1),
+    ]
+    for k, ds in enumerate(cases):
+        got, info = _run_plan(ds, kernel="cyclic", rows_per_lane=H)
+        pi, pj = oracle.all_pairs_list(ds.N)
+        L = ds.lengths.astype(np.int64)
+        bands = [max(ds.window, abs(int(L[a]) - int(L[b]))) for a, b in zip(pi, pj)]
+        windowed = sum(1 for (a, b), bb in zip(zip(pi, pj), bands) if bb < max(L[a], L[b]) - 1)
+        assert info["n_cyclic_items"] == windowed, (k, info)
+        assert_close(got, oracle_pairs(ds, pi, pj), tol=plain_tol(ds), what="cyclic H=%d case %d" % (H, k))
+        # same per-cell arithmetic as the strip kernel: results agree bit for bit
+        wave = run(ds, kernel="wave")
+        assert np.array_equal(got, wave), "cyclic H=%d case %d differs from the strip kernel" % (H, k)
+
+
+@pytest.mark.parametrize("w", [1, 17, 63])
+def test_band_edge_paths_all_kernels(w):
+    _gpu()
+    # equal lengths so that every family applies; cheapest paths hug the band edge
+    rng = np.random.default_rng(800 + w)
+    ds = synth.pack(band_edge_pairs(rng, [300] * 4, w), "edge", w)
+    pi, pj = oracle.all_pairs_list(ds.N)
+    ref = oracle_pairs(ds, pi, pj)
+    outs = {k: run(ds, kernel=k) for k in ("lane", "wave", "cyclic")}
+    for k, got in outs.items():
+        assert_close(got, ref, what="band edge w=%d %s" % (w, k))
+    assert np.array_equal(outs["lane"], outs["wave"]) and np.array_equal(outs["wave"], outs["cyclic"])
+
+
+def test_cyclic_band_zero_and_tiny_series():
+    _gpu()
+    # equal lengths with w=0 (diagonal only), and series of 1..3 points
+    rng = np.random.default_rng(77)
+    series = [synth.random_walk(rng, 200) for _ in range(5)] + [synth.random_walk(rng, L) for L in (1, 2, 3)]
+    for w in (0, 1, 2):
+        ds = synth.pack(series, "tiny", w)
+        pi, pj = oracle.all_pairs_list(ds.N)
+        ref = oracle_pairs(ds, pi, pj)
+        for H in (1, 4, 16):
+            got, info = _run_plan(ds, kernel="cyclic", rows_per_lane=H)
+            assert info["n_cyclic_items"] > 0
+            assert_close(got, ref, what="tiny w=%d H=%d" % (w, H))
+
+
+@pytest.mark.parametrize("frac", [0.05, 0.2])
+def test_auto_mixes_strip_and_cyclic(frac):
+    _gpu()
+    rng = np.random.default_rng(int(frac * 100))
+    lens = rng.integers(40, 1400, size=26)
+    series = [synth.random_walk(rng, int(L)) for L in lens]
+    ds = synth.pack(series, "mix", int(frac * lens.max()))
+    got, info = _run_plan(ds)
+    assert 0 < info["n_cyclic_items"] < ds.n_pairs, info
+    pi, pj = oracle.all_pairs_list(ds.N)
+    assert_close(got, oracle_pairs(ds, pi, pj), what="auto mix %.2f" % frac)
+    assert np.array_equal(got, run(ds, kernel="wave"))
+
+
+@pytest.mark.parametrize("H", [2, 12, 48])
+def test_wave_kernel_forced_rows_per_lane(H):
+    # a forced strip height gives the same bits as the automatic choice
+    ds = synth.small_random(seed=600 + H, N=14, len_lo=1, len_hi=64 * H, window=25)
+    assert np.array_equal(run(ds, kernel="wave", rows_per_lane=H), run(ds, kernel="wave"))
 
 
 # ---------------------------------------------------------------- batched plans, graph capture
