@@ -83,7 +83,7 @@ typedef struct dtw_options {
     int32_t dtype;  /* dtw_dtype */
     int32_t accum;  /* dtw_accum */
     int32_t kernel; /* dtw_kernel (0 = AUTO) */
-    int32_t flags;  /* bit 0: record HIP events around the DP kernels (plan API only) */
+    int32_t flags;  /* DTW_FLAG_* bits: TIMING (plan API only), NO_QUEUE */
     int32_t rows_per_lane; /* 0 = automatic.  Else the rows each lane holds in the WAVE and
                               CYCLIC kernels (1..64); a value with no instantiated kernel for a
                               pair returns DTW_ERR_UNSUPPORTED.  Ignored by LANE. */
@@ -91,6 +91,10 @@ typedef struct dtw_options {
 } dtw_options;
 
 #define DTW_FLAG_TIMING 1
+/* Launch one workgroup per work item (hardware dispatch order) instead of the
+ * default: a grid of resident workgroups pulling cost-sorted items from a
+ * device counter that every execute resets with a small kernel. */
+#define DTW_FLAG_NO_QUEUE 2
 
 typedef struct dtw_plan_s *dtw_plan;
 

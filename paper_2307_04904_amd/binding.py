@@ -19,6 +19,7 @@ DTYPES = {"f32": 0, "bf16": 1, "f16": 2}
 ACCUM = {"plain": 0, "kahan": 1, "fp64": 2}
 KERNELS = {"auto": 0, "lane": 1, "wave": 2, "cyclic": 3}
 DTW_FLAG_TIMING = 1
+DTW_FLAG_NO_QUEUE = 2
 
 EXPORTED = ["dtw_pairwise", "dtw_pairwise_ex", "dtw_plan_create", "dtw_plan_execute",
             "dtw_plan_last_kernel_ms", "dtw_plan_info", "dtw_plan_destroy", "dtw_band_cells",
@@ -147,10 +148,10 @@ def dtw_pairwise(series, lengths, offsets, N, window, out_condensed):
 
 
 def dtw_pairwise_ex(series, lengths, offsets, window, out_condensed, dtype="f32", accum="plain", kernel="auto",
-                    stream=None, rows_per_lane=0):
+                    stream=None, rows_per_lane=0, queue=True):
     """One dataset with options (blocking).  `series` holds f32, bf16 (as int16/uint16 bits) or f16 values."""
     d, keep = _make_dataset(series, lengths, offsets, window, out_condensed)
-    o = _options(dtype, accum, kernel, 0, stream, rows_per_lane)
+    o = _options(dtype, accum, kernel, 0 if queue else DTW_FLAG_NO_QUEUE, stream, rows_per_lane)
     _check(load().dtw_pairwise_ex(ctypes.byref(d), ctypes.byref(o)))
     del keep
 
@@ -162,7 +163,8 @@ class Plan:
     The tensors must stay alive, at the same address, while the plan exists.
     """
 
-    def __init__(self, datasets, dtype="f32", accum="plain", kernel="auto", timing=False, rows_per_lane=0):
+    def __init__(self, datasets, dtype="f32", accum="plain", kernel="auto", timing=False, rows_per_lane=0,
+                 queue=True):
         self._lib = load()
         arr = (dtw_dataset * max(1, len(datasets)))()
         self._keep = []
@@ -170,7 +172,8 @@ class Plan:
             d, keep = _make_dataset(series, lengths, offsets, window, out)
             arr[k] = d
             self._keep.append((keep, series, out))
-        o = _options(dtype, accum, kernel, DTW_FLAG_TIMING if timing else 0, False, rows_per_lane)
+        flags = (DTW_FLAG_TIMING if timing else 0) | (0 if queue else DTW_FLAG_NO_QUEUE)
+        o = _options(dtype, accum, kernel, flags, False, rows_per_lane)
         self._h = ctypes.c_void_p()
         _check(self._lib.dtw_plan_create(ctypes.byref(self._h), arr, len(datasets), ctypes.byref(o)))
 
@@ -212,12 +215,12 @@ def device_series(ds, device="cuda"):
     return t.to(device)
 
 
-def pairwise(ds, accum="plain", kernel="auto", device="cuda", out=None, rows_per_lane=0):
+def pairwise(ds, accum="plain", kernel="auto", device="cuda", out=None, rows_per_lane=0, queue=True):
     """Condensed DTW matrix of a synth.Dataset on the GPU, returned as a torch tensor (blocking)."""
     import torch
     series = device_series(ds, device)
     if out is None:
         out = torch.full((max(0, ds.n_pairs),), float("nan"), dtype=torch.float32, device=device)
     dtw_pairwise_ex(series, ds.lengths, ds.offsets, ds.window, out, dtype=ds.dtype, accum=accum, kernel=kernel,
-                    rows_per_lane=rows_per_lane)
+                    rows_per_lane=rows_per_lane, queue=queue)
     return out

@@ -85,6 +85,7 @@ struct WaveGroup {
     StripShape shape;  // G == 0: cyclic kernel with H = shape.H
     bool banded;
     int64_t begin, count;
+    int slots = 0;  // resident workgroups of the kernel (queue mode)
 };
 
 // Strip shape for a pair whose shorter series has n points: the instantiated
@@ -171,6 +172,8 @@ struct dtw_plan_s {
     DatasetInfo *d_ds = nullptr;
     LaneItem *d_lane = nullptr;
     WaveItem *d_wave = nullptr;
+    unsigned *d_queue = nullptr;  // one counter per wavefront group, zeroed by every execute
+    int n_queue = 0;
     std::vector<LaneGroup> lane_groups;
     std::vector<WaveGroup> wave_groups;
     dtw_plan_stats stats{};
@@ -191,7 +194,8 @@ int validate_options(const dtw_options *opt) {
         return fail(DTW_ERR_INVALID_ARG, "rows_per_lane=%d outside 0..64", opt->rows_per_lane);
     if (opt->kernel == DTW_KERNEL_CYCLIC && opt->accum != DTW_ACC_PLAIN)
         return fail(DTW_ERR_UNSUPPORTED, "the cyclic kernel needs PLAIN accumulation");
-    if (opt->flags & ~DTW_FLAG_TIMING) return fail(DTW_ERR_INVALID_ARG, "unknown flags 0x%x", opt->flags);
+    if (opt->flags & ~(DTW_FLAG_TIMING | DTW_FLAG_NO_QUEUE))
+        return fail(DTW_ERR_INVALID_ARG, "unknown flags 0x%x", opt->flags);
     return DTW_OK;
 }
 
@@ -387,12 +391,26 @@ int dtw_plan_create(dtw_plan *plan_out, const dtw_dataset *ds, int32_t n_dataset
     for (auto it : order) {
         auto &v = it->second;
         const StripShape sh{std::get<0>(it->first), std::get<1>(it->first)};
-        p->wave_groups.push_back(WaveGroup{sh, std::get<2>(it->first), (int64_t)wave_items.size(), (int64_t)v.size()});
+        p->wave_groups.push_back(
+            WaveGroup{sh, std::get<2>(it->first), (int64_t)wave_items.size(), (int64_t)v.size(), 0});
         for (auto &e : v) wave_items.push_back(e.second);
     }
     st.n_lane_items = static_cast<int32_t>(lane_items.size());
     st.n_wave_items = static_cast<int64_t>(wave_items.size());
-    st.n_launches = (p->nseries > 0 ? 1 : 0) + (int32_t)p->lane_groups.size() + (int32_t)p->wave_groups.size();
+    const int n_groups = (int)(p->lane_groups.size() + p->wave_groups.size());
+    for (const LaneGroup &g : p->lane_groups)
+        if (g.count > 0x7fffffff) {
+            delete p;
+            return fail(DTW_ERR_UNSUPPORTED, "more than 2^31-1 work items for one kernel");
+        }
+    for (const WaveGroup &g : p->wave_groups)
+        if (g.count > 0x7fffffff) {
+            delete p;
+            return fail(DTW_ERR_UNSUPPORTED, "more than 2^31-1 work items for one kernel");
+        }
+    const bool use_queue = !(flags & DTW_FLAG_NO_QUEUE) && !p->wave_groups.empty();
+    p->n_queue = use_queue ? (int)p->wave_groups.size() : 0;
+    st.n_launches = (p->nseries > 0 ? 1 : 0) + (use_queue ? 1 : 0) + n_groups;
 
     // ---- device allocation and upload ----
     ws_floats += 256;  // slack past the last slot
@@ -409,6 +427,8 @@ int dtw_plan_create(dtw_plan *plan_out, const dtw_dataset *ds, int32_t n_dataset
     off = align_up(off + lane_items.size() * sizeof(LaneItem), 256);
     const size_t o_wave = off;
     off = align_up(off + wave_items.size() * sizeof(WaveItem), 256);
+    const size_t o_queue = off;
+    off = align_up(off + p->n_queue * sizeof(unsigned), 256);
     p->dev_bytes = off;
     st.workspace_bytes = static_cast<int64_t>(off);
     p->stats = st;
@@ -430,6 +450,11 @@ int dtw_plan_create(dtw_plan *plan_out, const dtw_dataset *ds, int32_t n_dataset
     p->d_ds = reinterpret_cast<DatasetInfo *>(base + o_ds);
     p->d_lane = reinterpret_cast<LaneItem *>(base + o_lane);
     p->d_wave = reinterpret_cast<WaveItem *>(base + o_wave);
+    p->d_queue = p->n_queue ? reinterpret_cast<unsigned *>(base + o_queue) : nullptr;
+    if (use_queue) {  // grid of each launch: the workgroups the device holds at once
+        for (WaveGroup &g : p->wave_groups)
+            g.slots = g.shape.G == 0 ? cyclic_resident(g.shape.H) : strip_resident(accum, g.shape, g.banded);
+    }
     struct Up {
         void *dst;
         const void *src;
@@ -463,15 +488,21 @@ int dtw_plan_execute(dtw_plan p, void *stream) {
     hipError_t e = launch_stage(p->d_src, p->d_ser, p->ws, p->nseries, s);
     if (e != hipSuccess) return hip_fail(e, "staging kernel launch");
     if (p->ev0 && (e = hipEventRecord(p->ev0, s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+    if (p->n_queue && (e = launch_zero(p->d_queue, p->n_queue, s)) != hipSuccess)
+        return hip_fail(e, "queue reset kernel launch");
+    int q = 0;  // queue counter of the next group
     for (const LaneGroup &g : p->lane_groups) {
-        e = launch_lane(g.W, p->ws, p->d_ser, p->d_ds, p->d_lane + g.begin, g.count, s);
+        e = launch_lane(g.W, p->ws, p->d_ser, p->d_ds, p->d_lane + g.begin, (unsigned)g.count, s);
         if (e != hipSuccess) return hip_fail(e, "lane-band kernel launch");
     }
     for (const WaveGroup &g : p->wave_groups) {
+        unsigned *queue = p->d_queue ? p->d_queue + q++ : nullptr;
         if (g.shape.G == 0)
-            e = launch_cyclic(g.shape.H, p->ws, p->d_ser, p->d_ds, p->d_wave + g.begin, g.count, s);
+            e = launch_cyclic(g.shape.H, p->ws, p->d_ser, p->d_ds, p->d_wave + g.begin, (unsigned)g.count, queue,
+                              g.slots, s);
         else
-            e = launch_strip(p->accum, g.shape, g.banded, p->ws, p->d_ser, p->d_ds, p->d_wave + g.begin, g.count, s);
+            e = launch_strip(p->accum, g.shape, g.banded, p->ws, p->d_ser, p->d_ds, p->d_wave + g.begin,
+                             (unsigned)g.count, queue, g.slots, s);
         if (e != hipSuccess) return hip_fail(e, "wavefront kernel launch");
     }
     if (p->ev1) {
@@ -512,7 +543,7 @@ int dtw_pairwise_ex(const dtw_dataset *ds, const dtw_options *opt) {
     if (ds->N < 2) return DTW_OK;  // nothing to write, no HIP call
     dtw_options o{};
     if (opt) o = *opt;
-    o.flags = 0;
+    o.flags &= DTW_FLAG_NO_QUEUE;  // timing needs the plan API
     dtw_plan p = nullptr;
     rc = dtw_plan_create(&p, ds, 1, &o);
     if (rc) return rc;

@@ -50,11 +50,18 @@ struct WaveItem {
 };
 
 // Kernel launchers (dtw_kernels.hip).  All asynchronous on `stream`.
+// Wavefront launchers take the item count and a queue counter: with queue == nullptr
+// the grid has one workgroup per item; otherwise min(items, slots) resident
+// workgroups pull items from the counter, which must be zero at launch
+// (launch_zero).  `slots` comes from the matching *_resident function
+// (workgroups the device holds at once; 0 if it cannot be queried).
 hipError_t launch_stage(const SeriesSrc *src, const SeriesInfo *ser, float *ws, int32_t nseries,
                         hipStream_t stream);
+hipError_t launch_zero(unsigned *p, int n, hipStream_t stream);
 bool lane_width_supported(int W);
+// Lane-band items all cost the same: one workgroup per item, no queue.
 hipError_t launch_lane(int W, const float *ws, const SeriesInfo *ser, const DatasetInfo *dsi,
-                       const LaneItem *items, int64_t n_items, hipStream_t stream);
+                       const LaneItem *items, unsigned n_items, hipStream_t stream);
 // Strip shapes of the wavefront kernels: H rows per lane, G wavefronts per pair
 // (a workgroup of 64*G lanes covers up to 64*H*G rows of the shorter series).
 struct StripShape {
@@ -63,13 +70,16 @@ struct StripShape {
 // Instantiated shapes for an accumulation mode, in increasing row capacity;
 // returns their number (writes at most max_out of them).
 int strip_shapes(int accum, StripShape *out, int max_out);
+int strip_resident(int accum, StripShape shape, bool banded);
 hipError_t launch_strip(int accum, StripShape shape, bool banded, const float *ws, const SeriesInfo *ser,
-                        const DatasetInfo *dsi, const WaveItem *items, int64_t n_items, hipStream_t stream);
+                        const DatasetInfo *dsi, const WaveItem *items, unsigned n_items, unsigned *queue, int slots,
+                        hipStream_t stream);
 // Cyclic banded strips (PLAIN, window required): H rows per block, blocks
 // cycling over the 64 lanes of one wavefront; needs 64(H+1) >= 2b+H whenever
 // the pair has more than 64 blocks.
 int cyclic_shapes(int *H_out, int max_out);
+int cyclic_resident(int H);
 hipError_t launch_cyclic(int H, const float *ws, const SeriesInfo *ser, const DatasetInfo *dsi,
-                         const WaveItem *items, int64_t n_items, hipStream_t stream);
+                         const WaveItem *items, unsigned n_items, unsigned *queue, int slots, hipStream_t stream);
 
 }  // namespace dtwmi

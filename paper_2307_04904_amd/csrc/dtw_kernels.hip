@@ -57,6 +57,37 @@ __device__ __forceinline__ int64_t condensed_index(int i, int j, int N) {
 // ---------------------------------------------------------------------------
 // Staging: copy every series into its padded FP32 slot, widening 16-bit types
 // exactly, with +inf in the pads.
+// ---------------------------------------------------------------------------
+// Work distribution.  Without a queue a workgroup takes item blockIdx.x and
+// exits.  With a queue (a counter zeroed by k_zero before the launch) a grid
+// of resident workgroups pulls item indices with one atomic add each, in the
+// order the planner sorted the items (decreasing cost), until the counter
+// passes n_items.  The index is made wave-uniform so the item's fields stay
+// in scalar registers.
+template <int G>
+__device__ __forceinline__ unsigned next_item(unsigned *__restrict__ queue, unsigned *s_slot) {
+    if constexpr (G == 1) {
+        unsigned v = 0;
+        if (threadIdx.x == 0) v = atomicAdd(queue, 1u);
+        return __builtin_amdgcn_readfirstlane(v);
+    } else {
+        if (threadIdx.x == 0) *s_slot = atomicAdd(queue, 1u);
+        __syncthreads();
+        const unsigned v = __builtin_amdgcn_readfirstlane(*s_slot);
+        __syncthreads();  // every wavefront has read the slot before it is written again
+        return v;
+    }
+}
+
+// threadIdx.x as a value the compiler cannot see to be the same for every
+// item (it.ds >= 0, so the min is 0): keeps lane-derived per-row constants
+// inside the item loop instead of holding them in registers across items.
+__device__ __forceinline__ int item_lane(int ds) { return static_cast<int>(threadIdx.x) + min(ds, 0); }
+
+__global__ __launch_bounds__(64) void k_zero(unsigned *__restrict__ p, int n) {
+    for (int i = threadIdx.x; i < n; i += 64) p[i] = 0u;
+}
+
 __global__ __launch_bounds__(256) void k_stage(const SeriesSrc *__restrict__ src,
                                                const SeriesInfo *__restrict__ ser,
                                                float *__restrict__ ws) {
@@ -152,6 +183,8 @@ __device__ __forceinline__ void lane_group(float (&st)[W], const float (&x)[R], 
     if constexpr (CH + 1 < NCH) lane_group<W, R, C, CH + 1>(st, x, ybase, ynext, ycur, col0, L);
 }
 
+// Lane-band items have equal cost, so the kernel takes one item per workgroup
+// (hardware dispatch); an item loop would only add registers to this kernel.
 template <int W>
 __global__ __launch_bounds__(64) void k_lane(const float *__restrict__ ws, const SeriesInfo *__restrict__ ser,
                                              const DatasetInfo *__restrict__ dsi,
@@ -205,6 +238,7 @@ __global__ __launch_bounds__(64) void k_lane(const float *__restrict__ ws, const
         D.out[condensed_index(a, b, D.N)] = st[B];
     }
 }
+
 
 // ---------------------------------------------------------------------------
 // Wavefront strip kernels: one pair per workgroup of G wavefronts.
@@ -388,19 +422,17 @@ __device__ __forceinline__ void strip_step(int c, float yv, const XT &x, const t
 }
 
 template <class ACC, int H, int G, bool BANDED>
-__global__ __launch_bounds__(64 * G) void k_strip(const float *__restrict__ ws, const SeriesInfo *__restrict__ ser,
-                                                  const DatasetInfo *__restrict__ dsi,
-                                                  const WaveItem *__restrict__ items) {
+__device__ __forceinline__ void strip_item(const WaveItem it, const float *__restrict__ ws,
+                                           const SeriesInfo *__restrict__ ser, const DatasetInfo *__restrict__ dsi,
+                                           typename ACC::T (*ring)[kRing]) {
     using T = typename ACC::T;
     constexpr bool EVENTS = BANDED && H <= 32;  // wider strips test every cell
     constexpr bool PERCELL = BANDED && !EVENTS;
     constexpr int D = G > 1 ? kEpoch : 0;
     typedef typename XVec<H>::T xvec;
-    __shared__ T ring[G > 1 ? G - 1 : 1][kRing];
 
-    const int lane = threadIdx.x & 63;
+    const int lane = item_lane(it.ds) & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform within a wavefront
-    const WaveItem it = items[blockIdx.x];
     const DatasetInfo DI = dsi[it.ds];
     const SeriesInfo sr = ser[DI.series_base + it.rows];
     const SeriesInfo sc = ser[DI.series_base + it.cols];
@@ -498,6 +530,22 @@ __global__ __launch_bounds__(64 * G) void k_strip(const float *__restrict__ ws, 
         const int a = it.rows < it.cols ? it.rows : it.cols;
         const int b = it.rows < it.cols ? it.cols : it.rows;
         DI.out[condensed_index(a, b, DI.N)] = ACC::result(res);
+    }
+}
+
+template <class ACC, int H, int G, bool BANDED>
+__global__ __launch_bounds__(64 * G) void k_strip(const float *__restrict__ ws, const SeriesInfo *__restrict__ ser,
+                                                  const DatasetInfo *__restrict__ dsi,
+                                                  const WaveItem *__restrict__ items, unsigned *__restrict__ queue,
+                                                  unsigned n_items) {
+    __shared__ typename ACC::T ring[G > 1 ? G - 1 : 1][kRing];
+    __shared__ unsigned slot;
+    unsigned idx = blockIdx.x;
+    for (;;) {
+        if (queue) idx = next_item<G>(queue, &slot);
+        if (idx >= n_items) break;
+        strip_item<ACC, H, G, BANDED>(items[idx], ws, ser, dsi, ring);
+        if (!queue) break;
     }
 }
 
@@ -629,12 +677,10 @@ __device__ __forceinline__ void cyc_step(int s, CycLane<H> &c, typename XVec<H>:
 }
 
 template <int H>
-__global__ __launch_bounds__(64) void k_strip_cyc(const float *__restrict__ ws, const SeriesInfo *__restrict__ ser,
-                                                  const DatasetInfo *__restrict__ dsi,
-                                                  const WaveItem *__restrict__ items) {
+__device__ __forceinline__ void cyc_item(const WaveItem it, const float *__restrict__ ws,
+                                         const SeriesInfo *__restrict__ ser, const DatasetInfo *__restrict__ dsi) {
     typedef typename XVec<H>::T xvec;
-    const int lane = threadIdx.x;
-    const WaveItem it = items[blockIdx.x];
+    const int lane = item_lane(it.ds);
     const DatasetInfo DI = dsi[it.ds];
     const SeriesInfo sr = ser[DI.series_base + it.rows];
     const SeriesInfo sc = ser[DI.series_base + it.cols];
@@ -690,16 +736,40 @@ __global__ __launch_bounds__(64) void k_strip_cyc(const float *__restrict__ ws, 
     }
 }
 
+template <int H>
+__global__ __launch_bounds__(64) void k_strip_cyc(const float *__restrict__ ws, const SeriesInfo *__restrict__ ser,
+                                                  const DatasetInfo *__restrict__ dsi,
+                                                  const WaveItem *__restrict__ items, unsigned *__restrict__ queue,
+                                                  unsigned n_items) {
+    unsigned idx = blockIdx.x;
+    for (;;) {
+        if (queue) idx = next_item<1>(queue, nullptr);
+        if (idx >= n_items) break;
+        cyc_item<H>(items[idx], ws, ser, dsi);
+        if (!queue) break;
+    }
+}
+
 // ---------------------------------------------------------------------------
-// Launch tables.
-using LaneFn = hipError_t (*)(const float *, const SeriesInfo *, const DatasetInfo *, const LaneItem *,
-                              int64_t, hipStream_t);
+// Launch tables.  Every DP launcher takes the item count, the queue counter
+// (nullptr: one workgroup per item) and the grid size; its resident function
+// gives the workgroups of that kernel the device holds at once.
+int resident_blocks(const void *fn, int block) {
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, block, 0) != hipSuccess) return 0;
+    return cus * per;
+}
+
+using LaneFn = hipError_t (*)(const float *, const SeriesInfo *, const DatasetInfo *, const LaneItem *, unsigned,
+                              hipStream_t);
+using SlotsFn = int (*)();
 
 template <int I>
-hipError_t lane_launcher(const float *ws, const SeriesInfo *ser, const DatasetInfo *dsi,
-                         const LaneItem *items, int64_t n, hipStream_t st) {
-    hipLaunchKernelGGL(k_lane<2 * I + 1>, dim3(static_cast<unsigned>(n)), dim3(64), 0, st, ws, ser, dsi,
-                       items);
+hipError_t lane_launcher(const float *ws, const SeriesInfo *ser, const DatasetInfo *dsi, const LaneItem *items,
+                         unsigned n, hipStream_t st) {
+    hipLaunchKernelGGL(k_lane<2 * I + 1>, dim3(n), dim3(64), 0, st, ws, ser, dsi, items);
     return hipGetLastError();
 }
 
@@ -713,49 +783,77 @@ const std::array<LaneFn, (kLaneMaxW + 1) / 2> kLaneTable =
 
 template <class ACC, int H, int G>
 hipError_t strip_launch(bool banded, const float *ws, const SeriesInfo *ser, const DatasetInfo *dsi,
-                        const WaveItem *items, int64_t n, hipStream_t st) {
-    const dim3 grid(static_cast<unsigned>(n)), block(64 * G);
+                        const WaveItem *items, unsigned n, unsigned *queue, unsigned grid, hipStream_t st) {
+    const dim3 g(grid), block(64 * G);
     if (banded)
-        hipLaunchKernelGGL((k_strip<ACC, H, G, true>), grid, block, 0, st, ws, ser, dsi, items);
+        hipLaunchKernelGGL((k_strip<ACC, H, G, true>), g, block, 0, st, ws, ser, dsi, items, queue, n);
     else
-        hipLaunchKernelGGL((k_strip<ACC, H, G, false>), grid, block, 0, st, ws, ser, dsi, items);
+        hipLaunchKernelGGL((k_strip<ACC, H, G, false>), g, block, 0, st, ws, ser, dsi, items, queue, n);
     return hipGetLastError();
 }
 
+template <class ACC, int H, int G>
+int strip_slots(bool banded) {
+    return banded ? resident_blocks(reinterpret_cast<const void *>(&k_strip<ACC, H, G, true>), 64 * G)
+                  : resident_blocks(reinterpret_cast<const void *>(&k_strip<ACC, H, G, false>), 64 * G);
+}
+
 using StripFn = hipError_t (*)(bool, const float *, const SeriesInfo *, const DatasetInfo *, const WaveItem *,
-                               int64_t, hipStream_t);
+                               unsigned, unsigned *, unsigned, hipStream_t);
+using StripSlotsFn = int (*)(bool);
 struct StripEntry {
     int accum, H, G;
     StripFn fn;
+    StripSlotsFn slots;
 };
 
+#define DTWMI_STRIP(A, ACC, H, G) {A, H, G, &strip_launch<ACC, H, G>, &strip_slots<ACC, H, G>}
 // Instantiated shapes, per accumulation mode in increasing row capacity 64*H*G.
 const StripEntry kStrips[] = {
-    {0, 1, 1, &strip_launch<AccPlain, 1, 1>},   {0, 2, 1, &strip_launch<AccPlain, 2, 1>},
-    {0, 4, 1, &strip_launch<AccPlain, 4, 1>},   {0, 8, 1, &strip_launch<AccPlain, 8, 1>},
-    {0, 12, 1, &strip_launch<AccPlain, 12, 1>}, {0, 16, 1, &strip_launch<AccPlain, 16, 1>},
-    {0, 24, 1, &strip_launch<AccPlain, 24, 1>}, {0, 32, 1, &strip_launch<AccPlain, 32, 1>},
-    {0, 16, 2, &strip_launch<AccPlain, 16, 2>}, {0, 48, 1, &strip_launch<AccPlain, 48, 1>},
-    {0, 24, 2, &strip_launch<AccPlain, 24, 2>}, {0, 64, 1, &strip_launch<AccPlain, 64, 1>},
-    {0, 32, 2, &strip_launch<AccPlain, 32, 2>}, {0, 32, 4, &strip_launch<AccPlain, 32, 4>},
-    {0, 32, 8, &strip_launch<AccPlain, 32, 8>}, {0, 64, 8, &strip_launch<AccPlain, 64, 8>},
-    {1, 1, 1, &strip_launch<AccKahan, 1, 1>},   {1, 2, 1, &strip_launch<AccKahan, 2, 1>},
-    {1, 4, 1, &strip_launch<AccKahan, 4, 1>},   {1, 8, 1, &strip_launch<AccKahan, 8, 1>},
-    {1, 16, 1, &strip_launch<AccKahan, 16, 1>}, {1, 16, 2, &strip_launch<AccKahan, 16, 2>},
-    {1, 16, 4, &strip_launch<AccKahan, 16, 4>}, {1, 16, 8, &strip_launch<AccKahan, 16, 8>},
-    {1, 16, 16, &strip_launch<AccKahan, 16, 16>},
-    {2, 1, 1, &strip_launch<AccF64, 1, 1>},     {2, 2, 1, &strip_launch<AccF64, 2, 1>},
-    {2, 4, 1, &strip_launch<AccF64, 4, 1>},     {2, 8, 1, &strip_launch<AccF64, 8, 1>},
-    {2, 16, 1, &strip_launch<AccF64, 16, 1>},   {2, 16, 2, &strip_launch<AccF64, 16, 2>},
-    {2, 16, 4, &strip_launch<AccF64, 16, 4>},   {2, 16, 8, &strip_launch<AccF64, 16, 8>},
-    {2, 16, 16, &strip_launch<AccF64, 16, 16>},
+    DTWMI_STRIP(0, AccPlain, 1, 1),  DTWMI_STRIP(0, AccPlain, 2, 1),  DTWMI_STRIP(0, AccPlain, 4, 1),
+    DTWMI_STRIP(0, AccPlain, 8, 1),  DTWMI_STRIP(0, AccPlain, 12, 1), DTWMI_STRIP(0, AccPlain, 16, 1),
+    DTWMI_STRIP(0, AccPlain, 24, 1), DTWMI_STRIP(0, AccPlain, 32, 1), DTWMI_STRIP(0, AccPlain, 16, 2),
+    DTWMI_STRIP(0, AccPlain, 48, 1), DTWMI_STRIP(0, AccPlain, 24, 2), DTWMI_STRIP(0, AccPlain, 64, 1),
+    DTWMI_STRIP(0, AccPlain, 32, 2), DTWMI_STRIP(0, AccPlain, 32, 4), DTWMI_STRIP(0, AccPlain, 32, 8),
+    DTWMI_STRIP(0, AccPlain, 64, 8),
+    DTWMI_STRIP(1, AccKahan, 1, 1),  DTWMI_STRIP(1, AccKahan, 2, 1),  DTWMI_STRIP(1, AccKahan, 4, 1),
+    DTWMI_STRIP(1, AccKahan, 8, 1),  DTWMI_STRIP(1, AccKahan, 16, 1), DTWMI_STRIP(1, AccKahan, 16, 2),
+    DTWMI_STRIP(1, AccKahan, 16, 4), DTWMI_STRIP(1, AccKahan, 16, 8), DTWMI_STRIP(1, AccKahan, 16, 16),
+    DTWMI_STRIP(2, AccF64, 1, 1),    DTWMI_STRIP(2, AccF64, 2, 1),    DTWMI_STRIP(2, AccF64, 4, 1),
+    DTWMI_STRIP(2, AccF64, 8, 1),    DTWMI_STRIP(2, AccF64, 16, 1),   DTWMI_STRIP(2, AccF64, 16, 2),
+    DTWMI_STRIP(2, AccF64, 16, 4),   DTWMI_STRIP(2, AccF64, 16, 8),   DTWMI_STRIP(2, AccF64, 16, 16),
 };
+#undef DTWMI_STRIP
 
 template <int H>
 hipError_t cyc_launch(const float *ws, const SeriesInfo *ser, const DatasetInfo *dsi, const WaveItem *items,
-                      int64_t n, hipStream_t st) {
-    hipLaunchKernelGGL((k_strip_cyc<H>), dim3(static_cast<unsigned>(n)), dim3(64), 0, st, ws, ser, dsi, items);
+                      unsigned n, unsigned *queue, unsigned grid, hipStream_t st) {
+    hipLaunchKernelGGL((k_strip_cyc<H>), dim3(grid), dim3(64), 0, st, ws, ser, dsi, items, queue, n);
     return hipGetLastError();
+}
+
+template <int H>
+int cyc_slots() {
+    return resident_blocks(reinterpret_cast<const void *>(&k_strip_cyc<H>), 64);
+}
+
+using CycFn = hipError_t (*)(const float *, const SeriesInfo *, const DatasetInfo *, const WaveItem *, unsigned,
+                             unsigned *, unsigned, hipStream_t);
+struct CycEntry {
+    int H;
+    CycFn fn;
+    SlotsFn slots;
+};
+const CycEntry kCyclic[] = {{1, &cyc_launch<1>, &cyc_slots<1>},    {2, &cyc_launch<2>, &cyc_slots<2>},
+                            {4, &cyc_launch<4>, &cyc_slots<4>},    {8, &cyc_launch<8>, &cyc_slots<8>},
+                            {12, &cyc_launch<12>, &cyc_slots<12>}, {16, &cyc_launch<16>, &cyc_slots<16>},
+                            {24, &cyc_launch<24>, &cyc_slots<24>}, {32, &cyc_launch<32>, &cyc_slots<32>}};
+
+// Grid of a launch: one workgroup per item, or with a queue the resident
+// workgroups (at most one per item).
+unsigned grid_for(unsigned n, unsigned *queue, int slots) {
+    if (!queue || slots <= 0) return n;
+    return n < static_cast<unsigned>(slots) ? n : static_cast<unsigned>(slots);
 }
 
 }  // namespace
@@ -767,12 +865,18 @@ hipError_t launch_stage(const SeriesSrc *src, const SeriesInfo *ser, float *ws, 
     return hipGetLastError();
 }
 
+hipError_t launch_zero(unsigned *p, int n, hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, stream, p, n);
+    return hipGetLastError();
+}
+
 bool lane_width_supported(int W) { return W >= 1 && W <= kLaneMaxW && (W & 1); }
 
 hipError_t launch_lane(int W, const float *ws, const SeriesInfo *ser, const DatasetInfo *dsi,
-                       const LaneItem *items, int64_t n_items, hipStream_t stream) {
+                       const LaneItem *items, unsigned n_items, hipStream_t stream) {
     if (!lane_width_supported(W)) return hipErrorInvalidValue;
-    if (n_items <= 0) return hipSuccess;
+    if (n_items == 0) return hipSuccess;
     return kLaneTable[(W - 1) / 2](ws, ser, dsi, items, n_items, stream);
 }
 
@@ -786,40 +890,43 @@ int strip_shapes(int accum, StripShape *out, int max_out) {
     return k;
 }
 
+int strip_resident(int accum, StripShape shape, bool banded) {
+    for (const StripEntry &e : kStrips)
+        if (e.accum == accum && e.H == shape.H && e.G == shape.G) return e.slots(banded);
+    return 0;
+}
+
 hipError_t launch_strip(int accum, StripShape shape, bool banded, const float *ws, const SeriesInfo *ser,
-                        const DatasetInfo *dsi, const WaveItem *items, int64_t n_items, hipStream_t stream) {
-    if (n_items <= 0) return hipSuccess;
+                        const DatasetInfo *dsi, const WaveItem *items, unsigned n_items, unsigned *queue, int slots,
+                        hipStream_t stream) {
+    if (n_items == 0) return hipSuccess;
     for (const StripEntry &e : kStrips)
         if (e.accum == accum && e.H == shape.H && e.G == shape.G)
-            return e.fn(banded, ws, ser, dsi, items, n_items, stream);
+            return e.fn(banded, ws, ser, dsi, items, n_items, queue, grid_for(n_items, queue, slots), stream);
     return hipErrorInvalidValue;
 }
 
-const int kCyclicH[] = {1, 2, 4, 8, 12, 16, 24, 32};
-
 int cyclic_shapes(int *H_out, int max_out) {
     int k = 0;
-    for (int H : kCyclicH) {
-        if (H_out && k < max_out) H_out[k] = H;
+    for (const CycEntry &e : kCyclic) {
+        if (H_out && k < max_out) H_out[k] = e.H;
         ++k;
     }
     return k;
 }
 
+int cyclic_resident(int H) {
+    for (const CycEntry &e : kCyclic)
+        if (e.H == H) return e.slots();
+    return 0;
+}
+
 hipError_t launch_cyclic(int H, const float *ws, const SeriesInfo *ser, const DatasetInfo *dsi,
-                         const WaveItem *items, int64_t n_items, hipStream_t stream) {
-    if (n_items <= 0) return hipSuccess;
-    switch (H) {
-        case 1: return cyc_launch<1>(ws, ser, dsi, items, n_items, stream);
-        case 2: return cyc_launch<2>(ws, ser, dsi, items, n_items, stream);
-        case 4: return cyc_launch<4>(ws, ser, dsi, items, n_items, stream);
-        case 8: return cyc_launch<8>(ws, ser, dsi, items, n_items, stream);
-        case 12: return cyc_launch<12>(ws, ser, dsi, items, n_items, stream);
-        case 16: return cyc_launch<16>(ws, ser, dsi, items, n_items, stream);
-        case 24: return cyc_launch<24>(ws, ser, dsi, items, n_items, stream);
-        case 32: return cyc_launch<32>(ws, ser, dsi, items, n_items, stream);
-        default: return hipErrorInvalidValue;
-    }
+                         const WaveItem *items, unsigned n_items, unsigned *queue, int slots, hipStream_t stream) {
+    if (n_items == 0) return hipSuccess;
+    for (const CycEntry &e : kCyclic)
+        if (e.H == H) return e.fn(ws, ser, dsi, items, n_items, queue, grid_for(n_items, queue, slots), stream);
+    return hipErrorInvalidValue;
 }
 
 }  // namespace dtwmi

@@ -402,10 +402,38 @@ def test_plan_reexecute_with_new_values():
     plan.destroy()
 
 
+@pytest.mark.parametrize("accum", ["plain", "kahan"])
+def test_queue_and_hardware_dispatch_agree(accum):
+    # lane-band, strip (one and several wavefronts per pair) and cyclic groups,
+    # each launched as resident workgroups pulling from the device queue or as
+    # one workgroup per item: the same items give the same bits
+    _gpu()
+    dsets = [synth.small_random(seed=51, N=90, len_lo=80, len_hi=80, window=7),
+             synth.small_random(seed=52, N=40, len_lo=30, len_hi=700, window=25),
+             synth.small_random(seed=53, N=12, len_lo=1100, len_hi=1400, window=-1)]
+    got = {}
+    for q in (True, False):
+        plan, series, outs = _plan_for(dsets, accum=accum, queue=q)
+        for rep in range(2):  # the queue counters are reset by every execute
+            for o in outs:
+                o.fill_(float("nan"))
+            plan.execute()
+            torch.cuda.synchronize()
+        got[q] = [o.cpu().numpy()[:ds.n_pairs] for o, ds in zip(outs, dsets)]
+        plan.destroy()
+    for d, ds in enumerate(dsets):
+        assert not np.any(np.isnan(got[True][d])), "dataset %d: a pair was never written" % d
+        assert np.array_equal(got[True][d], got[False][d]), "dataset %d" % d
+    pi, pj = sample_pairs(dsets[1].N, 40, 5)
+    assert_close(got[True][1][condensed(pi, pj, dsets[1].N)], oracle_pairs(dsets[1], pi, pj),
+                 what="queue dispatch " + accum)
+
+
 def test_plan_replayed_from_hip_graph():
     _gpu()
     dsets = [synth.small_random(seed=41, N=50, len_lo=64, len_hi=64, window=9),
-             synth.small_random(seed=42, N=30, len_lo=20, len_hi=300, window=-1)]
+             synth.small_random(seed=42, N=30, len_lo=20, len_hi=300, window=-1),
+             synth.small_random(seed=43, N=30, len_lo=100, len_hi=900, window=40)]
     plan, series, outs = _plan_for(dsets)
     plan.execute()
     torch.cuda.synchronize()
