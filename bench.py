@@ -145,6 +145,8 @@ def main(argv=None):
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--kernel", default="auto", choices=["auto", "lane", "wave", "cyclic"])
     ap.add_argument("--accum", default="plain", choices=["plain", "kahan", "fp64"])
+    ap.add_argument("--autotune", action="store_true",
+                    help="plan with DTW_FLAG_AUTOTUNE (kernel instances measured per length/window bucket)")
     ap.add_argument("--dispatch", default="queue", choices=["queue", "hw"],
                     help="work distribution: resident workgroups pulling from a device queue, or one workgroup per item")
     ap.add_argument("--dtype", default="f32", choices=["f32", "bf16", "f16"],
@@ -178,9 +180,11 @@ def main(argv=None):
     torch.cuda.set_device(dev)
     series = [binding.device_series(ds, dev) for ds in dsets]
     outs = [torch.full((max(1, ds.n_pairs),), float("nan"), dtype=torch.float32, device=dev) for ds in dsets]
+    t_plan = time.perf_counter()
     plan = binding.Plan([(s_, ds.lengths, ds.offsets, ds.window, o) for s_, ds, o in zip(series, dsets, outs)],
                         dtype=dsets[0].dtype, accum=args.accum, kernel=args.kernel, timing=True,
-                        queue=args.dispatch == "queue")
+                        queue=args.dispatch == "queue", autotune=args.autotune)
+    plan_s = time.perf_counter() - t_plan
     info = plan.info()
     stream = torch.cuda.current_stream(dev)
 
@@ -228,7 +232,9 @@ def main(argv=None):
                    "window": [ds.window for ds in dsets] if len(dsets) > 1 else dsets[0].window,
                    "pairs": info["pairs"], "band_cells": cells, "swept_cells": info["computed_cells"],
                    "kernel": args.kernel, "accum": args.accum, "storage": dsets[0].dtype,
-                   "dispatch": args.dispatch},
+                   "dispatch": args.dispatch, "autotune": args.autotune,
+                   "plan_create_s": round(plan_s, 3), "tuned_buckets": info["n_tuned_buckets"],
+                   "tuned_changed": info["n_tuned_changed"]},
         "pct_peak_cell_rate": round(100.0 * value / (PEAK_LANE_OPS_T * 1e3 / OPS_PER_CELL), 2),
         "roofline": {
             "bound": "alu",

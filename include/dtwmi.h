@@ -83,7 +83,7 @@ typedef struct dtw_options {
     int32_t dtype;  /* dtw_dtype */
     int32_t accum;  /* dtw_accum */
     int32_t kernel; /* dtw_kernel (0 = AUTO) */
-    int32_t flags;  /* DTW_FLAG_* bits: TIMING (plan API only), NO_QUEUE */
+    int32_t flags;  /* DTW_FLAG_* bits: TIMING (plan API only), NO_QUEUE, AUTOTUNE */
     int32_t rows_per_lane; /* 0 = automatic.  Else the rows each lane holds in the WAVE and
                               CYCLIC kernels (1..64); a value with no instantiated kernel for a
                               pair returns DTW_ERR_UNSUPPORTED.  Ignored by LANE. */
@@ -95,6 +95,15 @@ typedef struct dtw_options {
  * default: a grid of resident workgroups pulling cost-sorted items from a
  * device counter that every execute resets with a small kernel. */
 #define DTW_FLAG_NO_QUEUE 2
+/* Plan creation measures, for every bucket of wavefront pairs with similar
+ * shorter length, longer length and window (half-octave ranges), up to four
+ * kernel instances that can run all of them (strip shapes and cyclic block
+ * heights, best by the cost model first) and gives the bucket the fastest.
+ * Timing launches run on the default stream, repeat a sample of the bucket's
+ * pairs until they fill the device, and write those pairs' results into the
+ * outputs (every execute overwrites them).  dtw_plan_describe reports the
+ * measurements.  Without it the cost model alone picks. */
+#define DTW_FLAG_AUTOTUNE 4
 
 typedef struct dtw_plan_s *dtw_plan;
 
@@ -108,6 +117,8 @@ typedef struct dtw_plan_stats {
     int32_t n_lane_items;    /* LANE work items (64 pairs each) */
     int64_t n_wave_items;    /* WAVE and CYCLIC work items (one pair each) */
     int64_t n_cyclic_items;  /* the CYCLIC ones among them */
+    int32_t n_tuned_buckets; /* buckets timed by DTW_FLAG_AUTOTUNE */
+    int32_t n_tuned_changed; /* of which the measurement overruled the cost model */
 } dtw_plan_stats;
 
 /*
@@ -144,6 +155,16 @@ int dtw_plan_execute(dtw_plan plan, void *stream);
 int dtw_plan_last_kernel_ms(dtw_plan plan, float *ms);
 
 int dtw_plan_info(dtw_plan plan, dtw_plan_stats *stats);
+
+/*
+ * JSON text describing the plan: kernel groups (instance, items, grid) and,
+ * with DTW_FLAG_AUTOTUNE, every timed bucket (length and band ranges, pairs,
+ * the cost model's pick, the chosen instance, microseconds per pair of each
+ * candidate).  Writes at most `size` bytes including the terminating NUL into
+ * buf (host) and the bytes needed into *needed; size 0 only queries *needed.
+ * A buffer that is too small gets an empty string and DTW_ERR_INVALID_ARG.
+ */
+int dtw_plan_describe(dtw_plan plan, char *buf, int64_t size, int64_t *needed);
 
 int dtw_plan_destroy(dtw_plan plan);
 

@@ -20,9 +20,10 @@ ACCUM = {"plain": 0, "kahan": 1, "fp64": 2}
 KERNELS = {"auto": 0, "lane": 1, "wave": 2, "cyclic": 3}
 DTW_FLAG_TIMING = 1
 DTW_FLAG_NO_QUEUE = 2
+DTW_FLAG_AUTOTUNE = 4
 
 EXPORTED = ["dtw_pairwise", "dtw_pairwise_ex", "dtw_plan_create", "dtw_plan_execute",
-            "dtw_plan_last_kernel_ms", "dtw_plan_info", "dtw_plan_destroy", "dtw_band_cells",
+            "dtw_plan_last_kernel_ms", "dtw_plan_info", "dtw_plan_describe", "dtw_plan_destroy", "dtw_band_cells",
             "dtw_last_error", "dtw_version"]
 
 
@@ -47,7 +48,8 @@ class dtw_plan_stats(ctypes.Structure):
     _fields_ = [("pairs", ctypes.c_int64), ("band_cells", ctypes.c_int64), ("computed_cells", ctypes.c_int64),
                 ("workspace_bytes", ctypes.c_int64), ("n_launches", ctypes.c_int32),
                 ("n_lane_items", ctypes.c_int32), ("n_wave_items", ctypes.c_int64),
-                ("n_cyclic_items", ctypes.c_int64)]
+                ("n_cyclic_items", ctypes.c_int64), ("n_tuned_buckets", ctypes.c_int32),
+                ("n_tuned_changed", ctypes.c_int32)]
 
 
 _lib = None
@@ -164,7 +166,7 @@ class Plan:
     """
 
     def __init__(self, datasets, dtype="f32", accum="plain", kernel="auto", timing=False, rows_per_lane=0,
-                 queue=True):
+                 queue=True, autotune=False):
         self._lib = load()
         arr = (dtw_dataset * max(1, len(datasets)))()
         self._keep = []
@@ -172,7 +174,8 @@ class Plan:
             d, keep = _make_dataset(series, lengths, offsets, window, out)
             arr[k] = d
             self._keep.append((keep, series, out))
-        flags = (DTW_FLAG_TIMING if timing else 0) | (0 if queue else DTW_FLAG_NO_QUEUE)
+        flags = ((DTW_FLAG_TIMING if timing else 0) | (0 if queue else DTW_FLAG_NO_QUEUE)
+                 | (DTW_FLAG_AUTOTUNE if autotune else 0))
         o = _options(dtype, accum, kernel, flags, False, rows_per_lane)
         self._h = ctypes.c_void_p()
         _check(self._lib.dtw_plan_create(ctypes.byref(self._h), arr, len(datasets), ctypes.byref(o)))
@@ -189,6 +192,15 @@ class Plan:
         st = dtw_plan_stats()
         _check(self._lib.dtw_plan_info(self._h, ctypes.byref(st)))
         return {name: int(getattr(st, name)) for name, _ in dtw_plan_stats._fields_}
+
+    def describe(self) -> dict:
+        """dtw_plan_describe parsed: kernel groups and autotuning measurements."""
+        import json
+        need = ctypes.c_int64()
+        _check(self._lib.dtw_plan_describe(self._h, None, ctypes.c_int64(0), ctypes.byref(need)))
+        buf = ctypes.create_string_buffer(int(need.value))
+        _check(self._lib.dtw_plan_describe(self._h, buf, ctypes.c_int64(need.value), ctypes.byref(need)))
+        return json.loads(buf.value.decode())
 
     def destroy(self):
         if self._h:

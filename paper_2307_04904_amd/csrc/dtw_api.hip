@@ -25,6 +25,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <set>
 #include <new>
 #include <string>
 #include <tuple>
@@ -88,22 +89,32 @@ struct WaveGroup {
     int slots = 0;  // resident workgroups of the kernel (queue mode)
 };
 
-// Strip shape for a pair whose shorter series has n points: the instantiated
-// shape of smallest row capacity 64*H*G >= n, restricted to H == force_h when
-// force_h > 0 ({0,0} if none fits).
-StripShape pick_strip(int accum, int n, int force_h) {
-    StripShape shapes[64];
-    const int k = strip_shapes(accum, shapes, 64);
-    for (int i = 0; i < k && i < 64; ++i)
-        if (64 * shapes[i].H * shapes[i].G >= n && (force_h <= 0 || shapes[i].H == force_h)) return shapes[i];
-    return StripShape{0, 0};
-}
 
 // Cost model shared by both wavefront families: wavefront-steps times VALU
-// instructions per step (3 per cell row plus loop overhead per step), from
-// the instruction mix of the compiled loops.
+// instructions per step (3 per cell row plus loop overhead per step, from the
+// instruction mix of the compiled loops), times a measured factor per kernel
+// instance: the median time per modelled instruction that DTW_FLAG_AUTOTUNE
+// found for that instance over the buckets of the 64-dataset batched workload
+// on MI355X, relative to the unwindowed 12-row strip.  The factors carry what
+// the instruction count misses: scalar work and waits of the window events
+// (windowed strips, cyclic kernel) and the occupancy of each register budget.
+constexpr int kMaxQueues = 128;  // queue counters of a plan (one per wavefront kernel group)
 constexpr int64_t kStripStepOverhead = 15;
 constexpr int64_t kCyclicStepOverhead = 20;
+
+struct CalEntry {
+    int H;
+    int strip_plain, strip_banded, cyclic;  // x100
+};
+const CalEntry kCal[] = {{1, 100, 300, 344},  {2, 100, 304, 339},  {4, 87, 236, 290},   {8, 95, 197, 239},
+                         {12, 103, 150, 214}, {16, 108, 151, 211}, {24, 112, 163, 231}, {32, 118, 171, 228},
+                         {48, 125, 180, 230}, {64, 130, 190, 230}};
+
+int64_t cal_factor(int H, int which) {  // which: 0 plain strip, 1 windowed strip, 2 cyclic
+    for (const CalEntry &c : kCal)
+        if (c.H >= H) return which == 0 ? c.strip_plain : which == 1 ? c.strip_banded : c.cyclic;
+    return which == 0 ? 130 : which == 1 ? 190 : 230;
+}
 
 // Steps a strip workgroup takes on an n x m pair (n = rows spread over lanes).
 int64_t strip_steps(StripShape sh, int64_t n, int64_t m) {
@@ -111,8 +122,13 @@ int64_t strip_steps(StripShape sh, int64_t n, int64_t m) {
     return m + lanes % 64 + (lanes / 64) * (64 + (sh.G > 1 ? 16 : 0));
 }
 
-int64_t strip_cost(StripShape sh, int64_t n, int64_t m) {
-    return sh.G * strip_steps(sh, n, m) * (3 * sh.H + kStripStepOverhead);
+// Workgroups of several wavefronts also pay the LDS hand-over and barriers
+// (measured: x1.2 for G = 2 against the same rows on one wavefront).
+constexpr int64_t kMultiWaveFactor = 120;
+
+int64_t strip_cost(StripShape sh, int64_t n, int64_t m, bool banded) {
+    const int64_t c = sh.G * strip_steps(sh, n, m) * (3 * sh.H + kStripStepOverhead) * cal_factor(sh.H, banded ? 1 : 0) / 100;
+    return sh.G > 1 ? c * kMultiWaveFactor / 100 : c;
 }
 
 // Cyclic kernel, rows = the longer series (n points), cols = the shorter (m),
@@ -127,7 +143,29 @@ bool cyclic_fits(int H, int64_t n, int64_t b) {
 int64_t cyclic_steps(int H, int64_t n, int64_t m) { return m + (n - 1) / H; }
 
 int64_t cyclic_cost(int H, int64_t n, int64_t m) {
-    return cyclic_steps(H, n, m) * (3 * H + kCyclicStepOverhead);
+    return cyclic_steps(H, n, m) * (3 * H + kCyclicStepOverhead) * cal_factor(H, 2) / 100;
+}
+
+// Strip shape for a pair whose shorter series has n points: of the two
+// instantiated shapes of smallest row capacity 64*H*G >= n (restricted to
+// H == force_h when force_h > 0), the cheaper by the cost model ({0,0} if none
+// fits).
+StripShape pick_strip(int accum, int n, int m, bool banded, int force_h) {
+    StripShape shapes[64];
+    const int k = strip_shapes(accum, shapes, 64);
+    StripShape best{0, 0};
+    int64_t best_cost = 0;
+    int taken = 0;
+    for (int i = 0; i < k && i < 64 && taken < 2; ++i)
+        if (64 * shapes[i].H * shapes[i].G >= n && (force_h <= 0 || shapes[i].H == force_h)) {
+            const int64_t c = strip_cost(shapes[i], n, m, banded);
+            if (!best.H || c < best_cost) {
+                best = shapes[i];
+                best_cost = c;
+            }
+            ++taken;
+        }
+    return best;
 }
 
 // Cheapest instantiated cyclic block height for the pair (0 if none fits);
@@ -158,6 +196,65 @@ int max_strip_rows(int accum) {
     return best;
 }
 
+// A pair for the wavefront families: `shorter` has n points, `longer` m >= n.
+struct WavePair {
+    int32_t d, shorter, longer, n, m;
+    int32_t b;  // effective band, -1 = none
+};
+
+// Kernel instance of a wavefront pair: a strip shape, or (G == 0) the cyclic
+// kernel with H rows per block.
+struct Choice {
+    int H = 0, G = 0;
+    bool cyclic() const { return G == 0 && H > 0; }
+    bool operator==(const Choice &o) const { return H == o.H && G == o.G; }
+    bool operator<(const Choice &o) const { return H != o.H ? H < o.H : G < o.G; }
+};
+
+int64_t choice_cost(int accum, Choice c, const WavePair &w) {
+    (void)accum;
+    return c.cyclic() ? cyclic_cost(c.H, w.m, w.n) : strip_cost(StripShape{c.H, c.G}, w.n, w.m, w.b >= 0);
+}
+
+int64_t choice_steps_cells(Choice c, const WavePair &w) {  // cells swept, padding included
+    return c.cyclic() ? (int64_t)64 * c.H * cyclic_steps(c.H, w.m, w.n)
+                      : (int64_t)64 * c.G * c.H * strip_steps(StripShape{c.H, c.G}, w.n, w.m);
+}
+
+// The cost model's choice for a pair (H == 0 if no instance fits).
+Choice model_choice(int accum, int kernel, int force_h, const WavePair &w) {
+    int64_t cyc_cost = 0;
+    const int cyc_h = (accum == DTW_ACC_PLAIN && w.b >= 0 && kernel != DTW_KERNEL_WAVE)
+                          ? pick_cyclic(w.m, w.n, w.b, force_h, &cyc_cost)
+                          : 0;
+    const StripShape sh =
+        kernel == DTW_KERNEL_CYCLIC && cyc_h ? StripShape{0, 0} : pick_strip(accum, w.n, w.m, w.b >= 0, force_h);
+    if (cyc_h && (!sh.H || cyc_cost < strip_cost(sh, w.n, w.m, w.b >= 0))) return Choice{cyc_h, 0};
+    return Choice{sh.H, sh.G};
+}
+
+// Work item of a pair for its kernel: strips spread the shorter series over
+// the lanes, the cyclic kernel the longer one.
+WaveItem make_item(Choice c, const WavePair &w) {
+    return c.cyclic() ? WaveItem{w.d, w.longer, w.shorter, w.b} : WaveItem{w.d, w.shorter, w.longer, w.b};
+}
+
+// Half-octave bucket of a positive length: 2*floor(log2 v) + (v >= 1.5 * 2^floor(log2 v)).
+int half_octave(int64_t v) {
+    int k = 0;
+    while ((v >> (k + 1)) > 0) ++k;
+    return 2 * k + (v >= (int64_t(3) << k) / 2 ? 1 : 0);
+}
+int64_t half_octave_lo(int h) { return h & 1 ? (int64_t(3) << (h / 2)) / 2 : int64_t(1) << (h / 2); }
+
+// Autotuning record of one (shorter length, longer length, band) bucket.
+struct TunedBucket {
+    int n_ho, m_ho, b_ho;  // half-octave buckets (b_ho of b+1; -1 = no window)
+    int64_t pairs;
+    Choice model, chosen;
+    std::vector<std::pair<Choice, float>> us_per_pair;  // measured candidates
+};
+
 }  // namespace
 
 struct dtw_plan_s {
@@ -179,6 +276,7 @@ struct dtw_plan_s {
     dtw_plan_stats stats{};
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     bool timed_once = false;
+    std::vector<TunedBucket> tuned;
 };
 
 namespace {
@@ -194,7 +292,7 @@ int validate_options(const dtw_options *opt) {
         return fail(DTW_ERR_INVALID_ARG, "rows_per_lane=%d outside 0..64", opt->rows_per_lane);
     if (opt->kernel == DTW_KERNEL_CYCLIC && opt->accum != DTW_ACC_PLAIN)
         return fail(DTW_ERR_UNSUPPORTED, "the cyclic kernel needs PLAIN accumulation");
-    if (opt->flags & ~(DTW_FLAG_TIMING | DTW_FLAG_NO_QUEUE))
+    if (opt->flags & ~(DTW_FLAG_TIMING | DTW_FLAG_NO_QUEUE | DTW_FLAG_AUTOTUNE))
         return fail(DTW_ERR_INVALID_ARG, "unknown flags 0x%x", opt->flags);
     return DTW_OK;
 }
@@ -221,6 +319,145 @@ void destroy_plan(dtw_plan p) {
 }
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// ---- autotuning (DTW_FLAG_AUTOTUNE) ----
+constexpr int kTuneSample = 32;      // distinct pairs timed per bucket
+constexpr int kTuneCandidates = 4;   // instances timed per bucket, best by the cost model first
+constexpr int kTuneMaxItems = 16384;  // items of one timing launch (sample repeated to fill the device)
+
+// Instances that can run every pair of a bucket: the cyclic heights that fit
+// all of them and the two smallest strip shapes that hold the longest shorter
+// series (strips only when the plan's kernel family allows them).
+std::vector<Choice> bucket_candidates(int accum, int kernel, int force_h, const std::vector<WavePair> &wp,
+                                      const std::vector<int64_t> &idx) {
+    int max_n = 0;
+    bool all_banded = true;
+    for (int64_t k : idx) {
+        max_n = std::max(max_n, wp[k].n);
+        all_banded = all_banded && wp[k].b >= 0;
+    }
+    std::vector<Choice> out;
+    if (accum == DTW_ACC_PLAIN && all_banded && kernel != DTW_KERNEL_WAVE) {
+        int hs[32];
+        const int kc = cyclic_shapes(hs, 32);
+        for (int i = 0; i < kc && i < 32; ++i) {
+            if (force_h > 0 && hs[i] != force_h) continue;
+            bool fits = true;
+            for (int64_t k : idx) fits = fits && cyclic_fits(hs[i], wp[k].m, wp[k].b);
+            if (fits) out.push_back(Choice{hs[i], 0});
+        }
+    }
+    if (!(kernel == DTW_KERNEL_CYCLIC && !out.empty())) {
+        StripShape shapes[64];
+        const int ks = strip_shapes(accum, shapes, 64);
+        int taken = 0;
+        for (int i = 0; i < ks && i < 64 && taken < 2; ++i)
+            if (64 * shapes[i].H * shapes[i].G >= max_n && (force_h <= 0 || shapes[i].H == force_h)) {
+                out.push_back(Choice{shapes[i].H, shapes[i].G});
+                ++taken;
+            }
+    }
+    return out;
+}
+
+// Time the candidate instances of every (shorter length, longer length, band)
+// bucket on the plan's own data and give each bucket's pairs the fastest.
+// Each timing launch repeats a sample of the bucket's pairs until it fills
+// the device once (its resident workgroups), so it measures throughput, not
+// the latency of a few pairs.  The kernels write the sampled pairs' results
+// into the outputs, which every execute overwrites.
+int autotune(dtw_plan p, const std::vector<WavePair> &wp, std::vector<Choice> &choice, int accum, int kernel,
+             int force_h) {
+    std::map<std::tuple<int, int, int>, std::vector<int64_t>> buckets;
+    for (size_t k = 0; k < wp.size(); ++k)
+        buckets[std::make_tuple(half_octave(wp[k].n), half_octave(wp[k].m),
+                                wp[k].b < 0 ? -1 : half_octave((int64_t)wp[k].b + 1))]
+            .push_back((int64_t)k);
+
+    hipStream_t s = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    WaveItem *d_items = nullptr;
+    std::vector<WaveItem> host(kTuneMaxItems);
+    std::set<std::pair<Choice, bool>> warmed;
+    int rc = DTW_OK;
+    hipError_t e = launch_stage(p->d_src, p->d_ser, p->ws, p->nseries, s);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e == hipSuccess) e = hipMalloc(&d_items, kTuneMaxItems * sizeof(WaveItem));
+    if (e != hipSuccess) rc = hip_fail(e, "autotune set-up");
+
+    for (auto it = buckets.begin(); rc == DTW_OK && it != buckets.end(); ++it) {
+        const std::vector<int64_t> &idx = it->second;
+        std::vector<Choice> cands = bucket_candidates(accum, kernel, force_h, wp, idx);
+        if (cands.size() < 2) continue;  // nothing to choose
+        std::vector<int64_t> sample;
+        const int64_t ns = std::min<int64_t>(kTuneSample, (int64_t)idx.size());
+        for (int64_t t = 0; t < ns; ++t) sample.push_back(idx[(size_t)(t * (int64_t)idx.size() / ns)]);
+        std::vector<std::pair<int64_t, Choice>> ranked;
+        for (const Choice &c : cands) {
+            int64_t cost = 0;
+            for (int64_t k : sample) cost += choice_cost(accum, c, wp[k]);
+            ranked.push_back({cost, c});
+        }
+        std::stable_sort(ranked.begin(), ranked.end(),
+                         [](const std::pair<int64_t, Choice> &a, const std::pair<int64_t, Choice> &b) {
+                             return a.first < b.first;
+                         });
+        if (ranked.size() > (size_t)kTuneCandidates) ranked.resize(kTuneCandidates);
+        const bool banded = std::get<2>(it->first) >= 0;
+        TunedBucket tb{std::get<0>(it->first), std::get<1>(it->first), std::get<2>(it->first),
+                       (int64_t)idx.size(), ranked[0].second, ranked[0].second, {}};
+        float best = 0.0f;
+        for (const auto &rc_pair : ranked) {
+            const Choice c = rc_pair.second;
+            const int slots = c.cyclic() ? cyclic_resident(c.H) : strip_resident(accum, StripShape{c.H, c.G}, banded);
+            const int64_t T = std::min<int64_t>(kTuneMaxItems, std::max<int64_t>((int64_t)sample.size(), slots));
+            for (int64_t t = 0; t < T; ++t) host[(size_t)t] = make_item(c, wp[sample[(size_t)(t % ns)]]);
+            e = hipMemcpy(d_items, host.data(), (size_t)T * sizeof(WaveItem), hipMemcpyHostToDevice);
+            auto run = [&]() {
+                return c.cyclic() ? launch_cyclic(c.H, p->ws, p->d_ser, p->d_ds, d_items, (unsigned)T, nullptr, 0, s)
+                                  : launch_strip(accum, StripShape{c.H, c.G}, banded, p->ws, p->d_ser, p->d_ds,
+                                                 d_items, (unsigned)T, nullptr, 0, s);
+            };
+            if (e == hipSuccess && !warmed.count({c, banded})) {  // first launch of an instance loads its code
+                e = run();
+                warmed.insert({c, banded});
+            }
+            if (e == hipSuccess) e = hipEventRecord(e0, s);
+            if (e == hipSuccess) e = run();
+            if (e == hipSuccess) e = hipEventRecord(e1, s);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) {
+                rc = hip_fail(e, "autotune timing launch");
+                break;
+            }
+            const float us = 1000.0f * ms / (float)T;
+            tb.us_per_pair.push_back({c, us});
+            if (tb.us_per_pair.size() == 1 || us < best) {
+                best = us;
+                tb.chosen = c;
+            }
+        }
+        if (rc != DTW_OK) break;
+        for (int64_t k : idx) choice[(size_t)k] = tb.chosen;
+        p->tuned.push_back(tb);
+    }
+    if (d_items) (void)hipFree(d_items);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    return rc;
+}
+
+std::string choice_name(Choice c) {
+    char buf[48];
+    if (c.cyclic())
+        snprintf(buf, sizeof buf, "cyclic:%d", c.H);
+    else
+        snprintf(buf, sizeof buf, "strip:%dx%d", c.H, c.G);
+    return buf;
+}
 
 }  // namespace
 
@@ -260,11 +497,9 @@ int dtw_plan_create(dtw_plan *plan_out, const dtw_dataset *ds, int32_t n_dataset
     std::vector<DatasetInfo> dsi;
     std::vector<LaneItem> lane_items;
     std::map<int, std::vector<LaneItem>> lane_by_w;
-    // wave items by kernel instance (H, G, banded); G == 0 is the cyclic kernel
-    std::map<std::tuple<int, int, bool>, std::vector<std::pair<int64_t, WaveItem>>> wave_by_kind;
+    std::vector<WavePair> wpairs;
     dtw_plan_stats st{};
     size_t ws_floats = 0;
-    const size_t elem = dtype == DTW_F32 ? 4 : 2;
 
     for (int32_t d = 0; d < n_datasets; ++d) {
         const dtw_dataset &D = ds[d];
@@ -289,7 +524,6 @@ int dtw_plan_create(dtw_plan *plan_out, const dtw_dataset *ds, int32_t n_dataset
             src.push_back(ss);
             ser.push_back(si);
         }
-        (void)elem;
         info.L = uniform ? D.lengths[0] : -1;
         dsi.push_back(info);
         const int64_t npairs = (int64_t)D.N * (D.N - 1) / 2;
@@ -325,39 +559,20 @@ int dtw_plan_create(dtw_plan *plan_out, const dtw_dataset *ds, int32_t n_dataset
                 for (int32_t j = i + 1; j < D.N; ++j) {
                     const int32_t ni = D.lengths[i], nj = D.lengths[j];
                     const bool swap = nj < ni;
-                    const int32_t shorter = swap ? j : i, longer = swap ? i : j;
-                    const int32_t n = std::min(ni, nj), m = std::max(ni, nj);
-                    const int64_t b = effective_band(D.window, n, m);
-                    const int64_t cells = band_cells(n, m, b);
-                    st.band_cells += cells;
-                    // cyclic candidate: PLAIN, a window, rows = the longer series
-                    int64_t cyc_cost = 0;
-                    const int cyc_h = (accum == DTW_ACC_PLAIN && b >= 0 && kernel != DTW_KERNEL_WAVE)
-                                          ? pick_cyclic(m, n, b, force_h, &cyc_cost)
-                                          : 0;
-                    const StripShape sh = kernel == DTW_KERNEL_CYCLIC && cyc_h ? StripShape{0, 0}
-                                                                               : pick_strip(accum, n, force_h);
-                    if (!sh.H && !cyc_h) {
+                    WavePair w{d, swap ? j : i, swap ? i : j, std::min(ni, nj), std::max(ni, nj), 0};
+                    w.b = static_cast<int32_t>(effective_band(D.window, w.n, w.m));
+                    st.band_cells += band_cells(w.n, w.m, w.b);
+                    if (!model_choice(accum, kernel, force_h, w).H) {
                         if (force_h > 0)
                             return fail(DTW_ERR_UNSUPPORTED,
-                                        "dataset %d: pair (%d,%d) (%d x %d points, band %lld): no kernel with "
+                                        "dataset %d: pair (%d,%d) (%d x %d points, band %d): no kernel with "
                                         "rows_per_lane=%d fits it",
-                                        d, i, j, n, m, (long long)b, force_h);
+                                        d, i, j, w.n, w.m, w.b, force_h);
                         return fail(DTW_ERR_UNSUPPORTED,
                                     "dataset %d: pair (%d,%d) has both series longer than %d points", d, i, j,
                                     max_strip_rows(accum));
                     }
-                    const int64_t s_cost = sh.H ? strip_cost(sh, n, m) : 0;
-                    if (cyc_h && (!sh.H || cyc_cost < s_cost)) {
-                        st.computed_cells += (int64_t)64 * cyc_h * cyclic_steps(cyc_h, m, n);
-                        ++st.n_cyclic_items;
-                        wave_by_kind[std::make_tuple(cyc_h, 0, true)].push_back(
-                            {cyc_cost, WaveItem{d, longer, shorter, (int32_t)b}});
-                    } else {
-                        st.computed_cells += (int64_t)64 * sh.G * sh.H * strip_steps(sh, n, m);
-                        wave_by_kind[std::make_tuple(sh.H, sh.G, b >= 0)].push_back(
-                            {s_cost, WaveItem{d, shorter, longer, (int32_t)b}});
-                    }
+                    wpairs.push_back(w);
                 }
             }
         }
@@ -370,49 +585,14 @@ int dtw_plan_create(dtw_plan *plan_out, const dtw_dataset *ds, int32_t n_dataset
     p->kernel = kernel;
     p->flags = flags;
     p->nseries = static_cast<int32_t>(ser.size());
-
-    std::vector<WaveItem> wave_items;
     for (auto &kv : lane_by_w) {
         p->lane_groups.push_back(LaneGroup{kv.first, (int64_t)lane_items.size(), (int64_t)kv.second.size()});
         lane_items.insert(lane_items.end(), kv.second.begin(), kv.second.end());
     }
-    // Inside a group, costlier pairs first; groups in decreasing order of their
-    // costliest pair.
-    std::vector<decltype(wave_by_kind)::iterator> order;
-    for (auto it = wave_by_kind.begin(); it != wave_by_kind.end(); ++it) {
-        std::stable_sort(it->second.begin(), it->second.end(),
-                         [](const std::pair<int64_t, WaveItem> &a, const std::pair<int64_t, WaveItem> &b) {
-                             return a.first > b.first;
-                         });
-        order.push_back(it);
-    }
-    std::stable_sort(order.begin(), order.end(),
-                     [](const auto &a, const auto &b) { return a->second[0].first > b->second[0].first; });
-    for (auto it : order) {
-        auto &v = it->second;
-        const StripShape sh{std::get<0>(it->first), std::get<1>(it->first)};
-        p->wave_groups.push_back(
-            WaveGroup{sh, std::get<2>(it->first), (int64_t)wave_items.size(), (int64_t)v.size(), 0});
-        for (auto &e : v) wave_items.push_back(e.second);
-    }
     st.n_lane_items = static_cast<int32_t>(lane_items.size());
-    st.n_wave_items = static_cast<int64_t>(wave_items.size());
-    const int n_groups = (int)(p->lane_groups.size() + p->wave_groups.size());
-    for (const LaneGroup &g : p->lane_groups)
-        if (g.count > 0x7fffffff) {
-            delete p;
-            return fail(DTW_ERR_UNSUPPORTED, "more than 2^31-1 work items for one kernel");
-        }
-    for (const WaveGroup &g : p->wave_groups)
-        if (g.count > 0x7fffffff) {
-            delete p;
-            return fail(DTW_ERR_UNSUPPORTED, "more than 2^31-1 work items for one kernel");
-        }
-    const bool use_queue = !(flags & DTW_FLAG_NO_QUEUE) && !p->wave_groups.empty();
-    p->n_queue = use_queue ? (int)p->wave_groups.size() : 0;
-    st.n_launches = (p->nseries > 0 ? 1 : 0) + (use_queue ? 1 : 0) + n_groups;
+    st.n_wave_items = static_cast<int64_t>(wpairs.size());
 
-    // ---- device allocation and upload ----
+    // ---- device allocation and upload of everything but the wavefront items ----
     ws_floats += 256;  // slack past the last slot
     size_t off = 0;
     const size_t o_ws = off;
@@ -426,12 +606,11 @@ int dtw_plan_create(dtw_plan *plan_out, const dtw_dataset *ds, int32_t n_dataset
     const size_t o_lane = off;
     off = align_up(off + lane_items.size() * sizeof(LaneItem), 256);
     const size_t o_wave = off;
-    off = align_up(off + wave_items.size() * sizeof(WaveItem), 256);
+    off = align_up(off + wpairs.size() * sizeof(WaveItem), 256);
     const size_t o_queue = off;
-    off = align_up(off + p->n_queue * sizeof(unsigned), 256);
+    off = align_up(off + kMaxQueues * sizeof(unsigned), 256);
     p->dev_bytes = off;
     st.workspace_bytes = static_cast<int64_t>(off);
-    p->stats = st;
 
     hipError_t e = hipGetDevice(&p->device);
     if (e != hipSuccess) {
@@ -450,11 +629,6 @@ int dtw_plan_create(dtw_plan *plan_out, const dtw_dataset *ds, int32_t n_dataset
     p->d_ds = reinterpret_cast<DatasetInfo *>(base + o_ds);
     p->d_lane = reinterpret_cast<LaneItem *>(base + o_lane);
     p->d_wave = reinterpret_cast<WaveItem *>(base + o_wave);
-    p->d_queue = p->n_queue ? reinterpret_cast<unsigned *>(base + o_queue) : nullptr;
-    if (use_queue) {  // grid of each launch: the workgroups the device holds at once
-        for (WaveGroup &g : p->wave_groups)
-            g.slots = g.shape.G == 0 ? cyclic_resident(g.shape.H) : strip_resident(accum, g.shape, g.banded);
-    }
     struct Up {
         void *dst;
         const void *src;
@@ -462,8 +636,7 @@ int dtw_plan_create(dtw_plan *plan_out, const dtw_dataset *ds, int32_t n_dataset
     } ups[] = {{p->d_src, src.data(), src.size() * sizeof(SeriesSrc)},
                {p->d_ser, ser.data(), ser.size() * sizeof(SeriesInfo)},
                {p->d_ds, dsi.data(), dsi.size() * sizeof(DatasetInfo)},
-               {p->d_lane, lane_items.data(), lane_items.size() * sizeof(LaneItem)},
-               {p->d_wave, wave_items.data(), wave_items.size() * sizeof(WaveItem)}};
+               {p->d_lane, lane_items.data(), lane_items.size() * sizeof(LaneItem)}};
     for (const Up &u : ups) {
         if (!u.bytes) continue;
         e = hipMemcpy(u.dst, u.src, u.bytes, hipMemcpyHostToDevice);
@@ -472,6 +645,75 @@ int dtw_plan_create(dtw_plan *plan_out, const dtw_dataset *ds, int32_t n_dataset
             return hip_fail(e, "hipMemcpy (plan upload)");
         }
     }
+
+    // ---- kernel instance of every wavefront pair: cost model, or measured ----
+    std::vector<Choice> choice(wpairs.size());
+    for (size_t k = 0; k < wpairs.size(); ++k) choice[k] = model_choice(accum, kernel, force_h, wpairs[k]);
+    if ((flags & DTW_FLAG_AUTOTUNE) && !wpairs.empty()) {
+        rc = autotune(p, wpairs, choice, accum, kernel, force_h);
+        if (rc) {
+            destroy_plan(p);
+            return rc;
+        }
+        st.n_tuned_buckets = static_cast<int32_t>(p->tuned.size());
+        for (const TunedBucket &t : p->tuned) st.n_tuned_changed += t.chosen == t.model ? 0 : 1;
+    }
+
+    // Group by kernel instance (H, G, banded); inside a group costlier pairs
+    // first, groups in decreasing order of their costliest pair.
+    std::map<std::tuple<int, int, bool>, std::vector<std::pair<int64_t, WaveItem>>> wave_by_kind;
+    for (size_t k = 0; k < wpairs.size(); ++k) {
+        const Choice c = choice[k];
+        const WavePair &w = wpairs[k];
+        st.computed_cells += choice_steps_cells(c, w);
+        st.n_cyclic_items += c.cyclic() ? 1 : 0;
+        wave_by_kind[std::make_tuple(c.H, c.G, c.cyclic() || w.b >= 0)].push_back(
+            {choice_cost(accum, c, w), make_item(c, w)});
+    }
+    std::vector<decltype(wave_by_kind)::iterator> order;
+    for (auto it = wave_by_kind.begin(); it != wave_by_kind.end(); ++it) {
+        std::stable_sort(it->second.begin(), it->second.end(),
+                         [](const std::pair<int64_t, WaveItem> &a, const std::pair<int64_t, WaveItem> &b) {
+                             return a.first > b.first;
+                         });
+        order.push_back(it);
+    }
+    std::stable_sort(order.begin(), order.end(),
+                     [](const auto &a, const auto &b) { return a->second[0].first > b->second[0].first; });
+    std::vector<WaveItem> wave_items;
+    wave_items.reserve(wpairs.size());
+    for (auto it : order) {
+        auto &v = it->second;
+        if (v.size() > 0x7fffffff) {
+            destroy_plan(p);
+            return fail(DTW_ERR_UNSUPPORTED, "more than 2^31-1 work items for one kernel");
+        }
+        const StripShape sh{std::get<0>(it->first), std::get<1>(it->first)};
+        p->wave_groups.push_back(
+            WaveGroup{sh, std::get<2>(it->first), (int64_t)wave_items.size(), (int64_t)v.size(), 0});
+        for (auto &e2 : v) wave_items.push_back(e2.second);
+    }
+    if (p->wave_groups.size() > (size_t)kMaxQueues) {
+        destroy_plan(p);
+        return fail(DTW_ERR_UNSUPPORTED, "more than %d wavefront kernel groups", kMaxQueues);
+    }
+    if (!wave_items.empty() &&
+        (e = hipMemcpy(p->d_wave, wave_items.data(), wave_items.size() * sizeof(WaveItem), hipMemcpyHostToDevice)) !=
+            hipSuccess) {
+        destroy_plan(p);
+        return hip_fail(e, "hipMemcpy (plan upload)");
+    }
+
+    const bool use_queue = !(flags & DTW_FLAG_NO_QUEUE) && !p->wave_groups.empty();
+    p->n_queue = use_queue ? (int)p->wave_groups.size() : 0;
+    p->d_queue = p->n_queue ? reinterpret_cast<unsigned *>(base + o_queue) : nullptr;
+    if (use_queue)  // grid of each launch: the workgroups the device holds at once
+        for (WaveGroup &g : p->wave_groups)
+            g.slots = g.shape.G == 0 ? cyclic_resident(g.shape.H) : strip_resident(accum, g.shape, g.banded);
+    st.n_launches = (p->nseries > 0 ? 1 : 0) + (use_queue ? 1 : 0) +
+                    (int32_t)(p->lane_groups.size() + p->wave_groups.size());
+    p->stats = st;
+
     if (flags & DTW_FLAG_TIMING) {
         if ((e = hipEventCreate(&p->ev0)) != hipSuccess || (e = hipEventCreate(&p->ev1)) != hipSuccess) {
             destroy_plan(p);
@@ -528,6 +770,60 @@ int dtw_plan_info(dtw_plan p, dtw_plan_stats *stats) {
     return DTW_OK;
 }
 
+int dtw_plan_describe(dtw_plan p, char *buf, int64_t size, int64_t *needed) {
+    if (!p || !needed) return fail(DTW_ERR_INVALID_ARG, "plan or needed is NULL");
+    if (size > 0 && !buf) return fail(DTW_ERR_INVALID_ARG, "buf is NULL with size > 0");
+    std::string j = "{\"lane_groups\": [";
+    char t[256];
+    for (size_t k = 0; k < p->lane_groups.size(); ++k) {
+        snprintf(t, sizeof t, "%s{\"W\": %d, \"items\": %lld}", k ? ", " : "", p->lane_groups[k].W,
+                 (long long)p->lane_groups[k].count);
+        j += t;
+    }
+    j += "], \"wave_groups\": [";
+    for (size_t k = 0; k < p->wave_groups.size(); ++k) {
+        const WaveGroup &g = p->wave_groups[k];
+        snprintf(t, sizeof t, "%s{\"kernel\": \"%s\", \"banded\": %s, \"items\": %lld, \"grid\": %lld}",
+                 k ? ", " : "", choice_name(Choice{g.shape.H, g.shape.G}).c_str(), g.banded ? "true" : "false",
+                 (long long)g.count, (long long)(p->n_queue && g.slots > 0 ? std::min<int64_t>(g.slots, g.count) : g.count));
+        j += t;
+    }
+    j += "], \"tuned\": [";
+    for (size_t k = 0; k < p->tuned.size(); ++k) {
+        const TunedBucket &b = p->tuned[k];
+        snprintf(t, sizeof t,
+                 "%s{\"n\": [%lld, %lld], \"m\": [%lld, %lld], \"band\": %s, \"pairs\": %lld, \"model\": \"%s\", "
+                 "\"chosen\": \"%s\", \"us_per_pair\": {",
+                 k ? ", " : "", (long long)half_octave_lo(b.n_ho), (long long)half_octave_lo(b.n_ho + 1) - 1,
+                 (long long)half_octave_lo(b.m_ho), (long long)half_octave_lo(b.m_ho + 1) - 1,
+                 b.b_ho < 0 ? "null" : "[]", (long long)b.pairs, choice_name(b.model).c_str(),
+                 choice_name(b.chosen).c_str());
+        std::string entry = t;
+        if (b.b_ho >= 0) {  // band range of the bucket: b + 1 in [lo, hi]
+            snprintf(t, sizeof t, "[%lld, %lld]", (long long)half_octave_lo(b.b_ho) - 1,
+                     (long long)half_octave_lo(b.b_ho + 1) - 2);
+            entry.replace(entry.find("[]"), 2, t);
+        }
+        j += entry;
+        for (size_t c = 0; c < b.us_per_pair.size(); ++c) {
+            snprintf(t, sizeof t, "%s\"%s\": %.4g", c ? ", " : "", choice_name(b.us_per_pair[c].first).c_str(),
+                     (double)b.us_per_pair[c].second);
+            j += t;
+        }
+        j += "}}";
+    }
+    j += "]}";
+    *needed = (int64_t)j.size() + 1;
+    if (size < *needed) {
+        if (size > 0) buf[0] = '\0';
+        return size > 0 ? fail(DTW_ERR_INVALID_ARG, "buffer of %lld bytes, %lld needed", (long long)size,
+                               (long long)*needed)
+                        : DTW_OK;
+    }
+    memcpy(buf, j.c_str(), j.size() + 1);
+    return DTW_OK;
+}
+
 int dtw_plan_destroy(dtw_plan p) {
     if (!p) return fail(DTW_ERR_INVALID_ARG, "plan is NULL");
     destroy_plan(p);
@@ -543,7 +839,7 @@ int dtw_pairwise_ex(const dtw_dataset *ds, const dtw_options *opt) {
     if (ds->N < 2) return DTW_OK;  // nothing to write, no HIP call
     dtw_options o{};
     if (opt) o = *opt;
-    o.flags &= DTW_FLAG_NO_QUEUE;  // timing needs the plan API
+    o.flags &= DTW_FLAG_NO_QUEUE | DTW_FLAG_AUTOTUNE;  // timing needs the plan API
     dtw_plan p = nullptr;
     rc = dtw_plan_create(&p, ds, 1, &o);
     if (rc) return rc;

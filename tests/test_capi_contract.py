@@ -80,11 +80,15 @@ def test_invalid_arguments_rejected_on_host():
     assert _call_ex(ok_len, ok_off, accum=3)[0] == B.DTW_ERR_INVALID_ARG
     assert _call_ex(ok_len, ok_off, kernel=9)[0] == B.DTW_ERR_INVALID_ARG
     assert _call_ex(ok_len, ok_off, flags=8)[0] == B.DTW_ERR_INVALID_ARG
+    assert _call_ex(ok_len, ok_off, kernel=3, accum=1)[0] == B.DTW_ERR_UNSUPPORTED  # cyclic needs PLAIN
     lib = B.load()
     assert lib.dtw_pairwise_ex(None, None) == B.DTW_ERR_INVALID_ARG
     assert lib.dtw_plan_destroy(None) == B.DTW_ERR_INVALID_ARG
     assert lib.dtw_plan_execute(None, None) == B.DTW_ERR_INVALID_ARG
     assert lib.dtw_band_cells(3, 3, 0, None) == B.DTW_ERR_INVALID_ARG
+    need = ctypes.c_int64()
+    assert lib.dtw_plan_describe(None, None, ctypes.c_int64(0), ctypes.byref(need)) == B.DTW_ERR_INVALID_ARG
+    assert _call_ex(ok_len, ok_off, flags=16)[0] == B.DTW_ERR_INVALID_ARG
 
 
 def test_fewer_than_two_series_is_a_no_op():

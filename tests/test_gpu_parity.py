@@ -429,6 +429,34 @@ def test_queue_and_hardware_dispatch_agree(accum):
                  what="queue dispatch " + accum)
 
 
+def test_autotuned_plan_matches_cost_model_plan():
+    # the tuner only changes which kernel instance runs a pair; every wavefront
+    # instance computes the same bits, so the results must not change
+    _gpu()
+    dsets = [synth.small_random(seed=61, N=40, len_lo=60, len_hi=1300, window=30),
+             synth.small_random(seed=62, N=30, len_lo=200, len_hi=900, window=-1),
+             synth.small_random(seed=63, N=60, len_lo=50, len_hi=50, window=5)]
+    got = {}
+    for tune in (False, True):
+        plan, series, outs = _plan_for(dsets, autotune=tune)
+        for o in outs:
+            o.fill_(float("nan"))
+        plan.execute()
+        torch.cuda.synchronize()
+        got[tune] = [o.cpu().numpy()[:ds.n_pairs] for o, ds in zip(outs, dsets)]
+        info, desc = plan.info(), plan.describe()
+        plan.destroy()
+    assert info["n_tuned_buckets"] == len(desc["tuned"]) > 0
+    for b in desc["tuned"]:
+        assert b["chosen"] in b["us_per_pair"] and b["model"] in b["us_per_pair"]
+        assert min(b["us_per_pair"].values()) == b["us_per_pair"][b["chosen"]] > 0
+    assert sum(g["items"] for g in desc["wave_groups"]) == dsets[0].n_pairs + dsets[1].n_pairs
+    for d, ds in enumerate(dsets):
+        assert np.array_equal(got[True][d], got[False][d]), "dataset %d" % d
+    pi, pj = sample_pairs(dsets[0].N, 50, 8)
+    assert_close(got[True][0][condensed(pi, pj, dsets[0].N)], oracle_pairs(dsets[0], pi, pj), what="autotuned")
+
+
 def test_plan_replayed_from_hip_graph():
     _gpu()
     dsets = [synth.small_random(seed=41, N=50, len_lo=64, len_hi=64, window=9),
