@@ -51,31 +51,44 @@ def make_datasets(name, dtype="f32"):
     return [{"c1": synth.config1, "c2": synth.config2, "c3": synth.config3, "c5": synth.config5}[name]()]
 
 
-def recorded_traffic(kernel_label):
-    """HBM bytes per launch recorded in profiles/ for the current kernel source, else None.
+def sources_sha256(paths):
+    """SHA-256 over the bytes of the given repository files, in order."""
+    import hashlib
+    h = hashlib.sha256()
+    for rel in paths:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
-    A profile file names the kernel source hash it was measured on
-    ("kernel_source_sha256: ...") and the scaled FETCH_SIZE + WRITE_SIZE total
-    ("traffic_bytes_per_launch: ..."); a changed source invalidates it.
+
+def recorded_traffic(kernel_label):
+    """HBM bytes per launch recorded in profiles/ for the current kernel sources, else None.
+
+    A profile file lists the sources its kernel is built from ("kernel_sources:
+    a b c"), their hash when it was measured ("kernel_source_sha256: ...") and
+    the scaled FETCH_SIZE + WRITE_SIZE total ("traffic_bytes_per_launch: ...");
+    a change to any of those sources invalidates it.
     """
     import glob
-    import hashlib
-    src = os.path.join(ROOT, "paper_2307_04904_amd", "csrc", "dtw_kernels.hip")
-    cur = hashlib.sha256(open(src, "rb").read()).hexdigest()
     for path in glob.glob(os.path.join(ROOT, "profiles", kernel_label + "*.md")):
-        text = open(path).read()
-        h = [l.split(":", 1)[1].strip() for l in text.splitlines() if l.startswith("kernel_source_sha256:")]
-        t = [l.split(":", 1)[1].strip() for l in text.splitlines() if l.startswith("traffic_bytes_per_launch:")]
-        if h and t and h[0] == cur:
-            return int(t[0])
+        fields = {}
+        for line in open(path).read().splitlines():
+            if ":" in line and line.split(":", 1)[0] in ("kernel_sources", "kernel_source_sha256",
+                                                         "traffic_bytes_per_launch"):
+                k, v = line.split(":", 1)
+                fields[k] = v.strip()
+        if len(fields) == 3 and sources_sha256(fields["kernel_sources"].split()) == fields["kernel_source_sha256"]:
+            return int(fields["traffic_bytes_per_launch"])
     return None
 
 
 def cpu_baseline(dsets, gpu_outs, target_s):
     """Time the FP64 oracle on a seeded sample of pairs (all host cores) and check the GPU on them.
 
-    The sample draws pairs uniformly over all datasets' pairs; the oracle runs
-    dataset by dataset on all host cores.
+    The sample draws pairs uniformly over all datasets' pairs, puts every
+    dataset's series in one buffer and times one threaded oracle call over
+    them.  A pilot sample, grown until it takes half a second, sets the size
+    of the timed sample to about target_s seconds of oracle work.
     """
     import oracle
     from paper_2307_04904_amd import synth
@@ -116,8 +129,13 @@ def cpu_baseline(dsets, gpu_outs, target_s):
             k += len(a)
         return t, refs, cells, threads
 
-    t_cal, _, _, _ = run(sample(256))
-    k = int(min(npairs.sum(), max(256, 256 * target_s / max(t_cal, 1e-3))))
+    k_cal = 64
+    while True:
+        t_cal, _, _, _ = run(sample(k_cal))
+        if t_cal >= 0.5 or k_cal >= npairs.sum():
+            break
+        k_cal *= 4
+    k = int(min(npairs.sum(), max(k_cal, k_cal * target_s / max(t_cal, 1e-3))))
     smp = sample(k)
     t, refs, c, threads = run(smp)
     rels, zero_bad, n = [], 0, 0
@@ -151,7 +169,7 @@ def main(argv=None):
                     help="work distribution: resident workgroups pulling from a device queue, or one workgroup per item")
     ap.add_argument("--dtype", default="f32", choices=["f32", "bf16", "f16"],
                     help="storage type of the series (the long-series workload's precision study)")
-    ap.add_argument("--cpu-seconds", type=float, default=10.0, help="target duration of the CPU oracle sample")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target duration of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration-mb", type=float, default=0.0,
                     help="only run 5 device-to-device copies of this many MiB (reference for HBM byte counters)")

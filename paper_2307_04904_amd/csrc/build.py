@@ -13,7 +13,7 @@ PKG = os.path.dirname(HERE)
 ROOT = os.path.dirname(PKG)
 OUT_DIR = os.path.join(PKG, "_build")
 LIB = os.path.join(OUT_DIR, "libdtwmi.so")
-SOURCES = ["dtw_kernels.hip", "dtw_api.hip"]
+SOURCES = ["dtw_stage.hip", "dtw_lane.hip", "dtw_strip.hip", "dtw_cyclic.hip", "dtw_api.hip"]
 ARCH = os.environ.get("DTWMI_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [
@@ -21,7 +21,6 @@ FLAGS = [
     "-O3",
     "-std=c++17",
     "-fPIC",
-    "-shared",
     # exact IEEE ops as written: no contraction (the Kahan and FP64 kernels rely on it)
     "-ffp-contract=off",
     # no packed FP32 instructions anywhere
@@ -29,21 +28,40 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
-    os.makedirs(OUT_DIR, exist_ok=True)
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = ["hipcc"] + FLAGS + ["-I", os.path.join(ROOT, "include"), "-I", HERE]
-    cmd += [os.path.join(HERE, s) for s in SOURCES] + ["-o", tmp]
+NOISE = ("packed-fp32-ops' is not a recognized feature", "argument unused during compilation")
+
+
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
-    noise = ("packed-fp32-ops' is not a recognized feature", "argument unused during compilation")
-    msgs = [l for l in (res.stdout + res.stderr).splitlines() if l.strip() and not any(n in l for n in noise)]
+    msgs = [l for l in (res.stdout + res.stderr).splitlines() if l.strip() and not any(n in l for n in NOISE)]
     if res.returncode != 0:
-        raise RuntimeError("hipcc failed (%d):\n%s" % (res.returncode, "\n".join(msgs)))
+        raise RuntimeError("hipcc failed (%d): %s\n%s" % (res.returncode, " ".join(cmd), "\n".join(msgs)))
     if verbose and msgs:
         print("\n".join(msgs))
-    os.replace(tmp, LIB)
+
+
+def build(verbose: bool = False, jobs: int = 0) -> str:
+    """Compile every source to an object (in parallel), then link the shared library."""
+    from concurrent.futures import ThreadPoolExecutor
+    os.makedirs(OUT_DIR, exist_ok=True)
+    inc = ["-I", os.path.join(ROOT, "include"), "-I", HERE]
+    tag = "%d" % os.getpid()
+    objs = [os.path.join(OUT_DIR, os.path.splitext(s)[0] + ".o." + tag) for s in SOURCES]
+    cmds = [["hipcc"] + FLAGS + inc + ["-c", os.path.join(HERE, s), "-o", o] for s, o in zip(SOURCES, objs)]
+    jobs = jobs or min(len(cmds), os.cpu_count() or 1, 8)
+    try:
+        with ThreadPoolExecutor(max_workers=jobs) as pool:
+            for f in [pool.submit(_run, c, verbose) for c in cmds]:
+                f.result()
+        tmp = LIB + ".tmp" + tag
+        _run(["hipcc", "--offload-arch=" + ARCH, "-shared", "-fPIC"] + objs + ["-o", tmp], verbose)
+        os.replace(tmp, LIB)
+    finally:
+        for o in objs:
+            if os.path.exists(o):
+                os.remove(o)
     return LIB
 
 

@@ -58,6 +58,9 @@ struct WaveItem {
 hipError_t launch_stage(const SeriesSrc *src, const SeriesInfo *ser, float *ws, int32_t nseries,
                         hipStream_t stream);
 hipError_t launch_zero(unsigned *p, int n, hipStream_t stream);
+// Workgroups of `block` threads of kernel `fn` the current device holds at
+// once (CUs x occupancy per CU; 0 if it cannot be queried).
+int resident_blocks(const void *fn, int block);
 bool lane_width_supported(int W);
 // Lane-band items all cost the same: one workgroup per item, no queue.
 hipError_t launch_lane(int W, const float *ws, const SeriesInfo *ser, const DatasetInfo *dsi,

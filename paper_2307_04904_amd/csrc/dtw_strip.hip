@@ -1,0 +1,357 @@
+// Wavefront strip kernels for the all-pairs DTW matrix: one pair per
+// workgroup of 1..16 wavefronts, each lane owning a strip of rows of the
+// shorter series; FP32, Kahan-compensated FP32 or FP64 accumulation.
+// Evaluates Eq. (c) of the paper ("Mathematical background") under the window
+// rule of the Introduction.
+#include "dtw_device.h"
+
+namespace dtwmi {
+namespace {
+
+// ---------------------------------------------------------------------------
+// Wavefront strip kernels: one pair per workgroup of G wavefronts.
+//
+// Lane l of wavefront g owns rows [(64g+l)H, (64g+l)H+H) of the row series
+// and at step s processes column s - l - g(64+D) (anti-diagonal skew).  Each
+// step updates a whole strip column: H cells in order, each cell's "up" being
+// the cell just computed above it.  The bottom cell goes to lane l+1 with a
+// DPP wave_shr:1 move; the previous step's received value is the diagonal.
+// Between wavefronts of one workgroup the bottom row of lane 63 is handed
+// over through an LDS ring: wavefront g lags wavefront g-1 by D = K extra
+// steps and the workgroup meets at a barrier every K steps, so a value is
+// always read at least one barrier after it was written.  State per lane is
+// 2H cells, ping-ponged over two unrolled steps.
+
+// Accumulation policies: cell(x, y, diag, up, left) evaluates Eq. (c).
+struct AccPlain {  // FP32: sub, min3, fused multiply-add
+    using T = float;
+    __device__ static T inf() { return kInf; }
+    __device__ static T zero() { return 0.0f; }
+    __device__ static T cell(float xe, float yv, T diag, T up, T left) {
+        const float d = xe - yv;
+        return fmaf(d, d, min3f(diag, up, left));
+    }
+    __device__ static float result(T v) { return v; }
+};
+
+// Kahan-compensated FP32: each cell carries (s, c) with the true value close
+// to s - c.  The min compares the running sums s (ties prefer diag, then up,
+// then left) and takes the compensation of the chosen predecessor; the local
+// cost is then added with Kahan's compensated step.  An unreachable cell (s =
+// +inf) gets c = NaN from inf - inf; that is harmless: a reachable cell has a
+// finite predecessor, fminf ignores quiet NaNs and NaN never compares equal,
+// so such a c is never selected.
+struct KahanCell {
+    float s, c;
+};
+struct AccKahan {
+    using T = KahanCell;
+    __device__ static T inf() { return {kInf, 0.0f}; }
+    __device__ static T zero() { return {0.0f, 0.0f}; }
+    __device__ static T cell(float xe, float yv, T diag, T up, T left) {
+        const float d = xe - yv;
+        const float q = d * d;
+        const float p = min3f(diag.s, up.s, left.s);
+        const float c1 = (p == up.s) ? up.c : left.c;
+        const float cs = (p == diag.s) ? diag.c : c1;
+        const float yk = q - cs;
+        const float t = p + yk;
+        return {t, (t - p) - yk};
+    }
+    __device__ static float result(T v) { return v.s < kInf ? v.s - v.c : v.s; }
+};
+
+// FP64: the operations of an IEEE double evaluation of Eq. (c) -- difference,
+// product, min of three, sum -- in that order, so the result equals the FP64
+// reference rounded once to FP32.  (An inadmissible cell's 1e30 x gives a
+// cost of ~1e60 instead of +inf; every admissible cell has an admissible
+// finite predecessor, so such values are never the minimum of one.)
+struct AccF64 {
+    using T = double;
+    __device__ static T inf() { return kInfD; }
+    __device__ static T zero() { return 0.0; }
+    __device__ static T cell(float xe, float yv, T diag, T up, T left) {
+        const double d = static_cast<double>(xe) - static_cast<double>(yv);
+        const double t = fmin(fmin(diag, up), left);
+        return d * d + t;
+    }
+    __device__ static float result(T v) { return static_cast<float>(v); }
+};
+
+__device__ __forceinline__ KahanCell lane_shift_down(KahanCell v, KahanCell fill) {
+    return {lane_shift_down(v.s, fill.s), lane_shift_down(v.c, fill.c)};
+}
+
+// Window edges by row events.  With the skew of this wavefront, a row of the
+// strip enters the window (column r-b) at step l(H+1)+h-be and leaves it
+// (column r+b+1) at step l(H+1)+h+bx+1, where l, h are the wave-local lane and
+// strip row and be, bx are the band shifted by the wavefront's offset: at most
+// one row enters and one row leaves per step, and the lane and strip row of
+// each event are wave-uniform.  A row outside the window has its x replaced
+// by 1e30 (its local cost overflows), so the cell loop itself carries no test.
+struct BandEvents {
+    RowCounter en, ex;
+    int nloc, col_shift;  // rows of the pair from this wavefront's first row; column = s - l - col_shift
+
+    template <int H>
+    __device__ __forceinline__ void init(int band, int n_rows, int wave, int D) {
+        const int row0 = wave * 64 * H;
+        nloc = n_rows - row0;
+        col_shift = wave * (64 + D);
+        const int shift = row0 + col_shift;
+        en.init<H>(band - shift);       // entry at step s: s + b - shift = l(H+1) + h
+        ex.init<H>(-band - shift - 1);  // exit at step s:  s - b - shift - 1 = l(H+1) + h
+    }
+
+    // Apply the events of step s (counters are at step s on entry), then advance.
+    template <int H>
+    __device__ __forceinline__ void step(int s, typename XVec<H>::T &xe, const typename XVec<H>::T &xr, int lane) {
+        if (en.h < H && en.q >= 0 && en.q < 64 && en.q * H + en.h < nloc && s - en.q - col_shift > 0) {
+            const float cur = xe[en.h];
+            const float v = xr[en.h];
+            xe[en.h] = lane == en.q ? v : cur;
+        }
+        en.advance<H>();
+        if (ex.h < H && ex.q >= 0 && ex.q < 64 && ex.q * H + ex.h < nloc) {
+            const float cur = xe[ex.h];
+            xe[ex.h] = lane == ex.q ? kBig : cur;
+        }
+        ex.advance<H>();
+    }
+};
+
+// True iff row rbase+h and column c are outside the window (off = rbase - c).
+__device__ __forceinline__ bool outside(int off, int h, int band) {
+    const int o = off + h;
+    return o > band || o < -band;
+}
+
+constexpr int kEpoch = 16;     // steps between workgroup barriers (multi-wavefront strips)
+constexpr int kRing = 64;      // LDS ring slots per wavefront boundary (>= 2*kEpoch + 2)
+
+template <class ACC, int H, bool PERCELL, typename XT>
+__device__ __forceinline__ void strip_step(int c, float yv, const XT &x, const typename ACC::T (&O)[H],
+                                           typename ACC::T (&N)[H], typename ACC::T &up_in,
+                                           typename ACC::T &diag_in, int rbase, int band) {
+    using T = typename ACC::T;
+    T diag = diag_in, up = up_in;
+    const int off = rbase - c;
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+        float xe = x[h];
+        if constexpr (PERCELL) xe = outside(off, h, band) ? kBig : xe;
+        const T v = ACC::cell(xe, yv, diag, up, O[h]);
+        diag = O[h];
+        up = v;
+        N[h] = v;
+    }
+}
+
+template <class ACC, int H, int G, bool BANDED>
+__device__ __forceinline__ void strip_item(const WaveItem it, const float *__restrict__ ws,
+                                           const SeriesInfo *__restrict__ ser, const DatasetInfo *__restrict__ dsi,
+                                           typename ACC::T (*ring)[kRing]) {
+    using T = typename ACC::T;
+    constexpr bool EVENTS = BANDED && H <= 32;  // wider strips test every cell
+    constexpr bool PERCELL = BANDED && !EVENTS;
+    constexpr int D = G > 1 ? kEpoch : 0;
+    typedef typename XVec<H>::T xvec;
+
+    const int lane = item_lane(it.ds) & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform within a wavefront
+    const DatasetInfo DI = dsi[it.ds];
+    const SeriesInfo sr = ser[DI.series_base + it.rows];
+    const SeriesInfo sc = ser[DI.series_base + it.cols];
+    const int n = sr.len, m = sc.len, band = it.band;
+    const float *__restrict__ xp = ws + sr.pstart;
+    const float *__restrict__ yp = ws + sc.pstart;
+    const int rbase = (wave * 64 + lane) * H;
+    const int skew = lane + wave * (64 + D);  // column = s - skew
+    const int Lf = (n - 1) / H, wf = Lf >> 6, lf = Lf & 63, hf = (n - 1) - Lf * H;
+    const int sfinal = (m - 1) + lf + wf * (64 + D);  // step computing cell (n-1, m-1)
+
+    float xa[H];
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+        const int r = rbase + h;
+        const float v = xp[r < n ? r : n - 1];
+        xa[h] = r < n ? v : 0.0f;  // rows past n never feed row n-1
+    }
+    xvec xr, x;
+    T A[H], Bv[H];
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+        const int r = rbase + h;
+        xr[h] = xa[h];
+        x[h] = (!EVENTS || (r < n && r - band <= 0)) ? xa[h] : kBig;
+        A[h] = ACC::inf();
+        Bv[h] = ACC::inf();
+    }
+    BandEvents ev;
+    if constexpr (EVENTS) ev.init<H>(band, n, wave, D);
+    if constexpr (G > 1) {
+        for (int k = threadIdx.x; k < (G - 1) * kRing; k += 64 * G) ring[k / kRing][k % kRing] = ACC::inf();
+        __syncthreads();
+    }
+    T up_in = ACC::inf();
+    T diag_in = (lane == 0 && wave == 0) ? ACC::zero() : ACC::inf();  // c(0,0) of the 1-based recurrence
+
+    // y of column s - skew; the +inf pads cover the columns a single wavefront
+    // reads ([-63, m+64]), later wavefronts clamp into [-1, m]
+    auto yat = [&](int s) {
+        const int c = s - skew;
+        if constexpr (G == 1) return yp[c];
+        return yp[c < -1 ? -1 : (c > m ? m : c)];
+    };
+    // value handed to lane 0 of this wavefront (LDS ring for wavefronts after the first)
+    auto boundary = [&](int s) -> T {
+        if constexpr (G > 1) {
+            if (wave > 0) return ring[wave - 1][(s - skew) & (kRing - 1)];
+        }
+        return ACC::inf();
+    };
+    auto publish = [&](int s, const T &bottom) {
+        if constexpr (G > 1) {
+            if (lane == 63 && wave < G - 1) ring[wave][(s - skew) & (kRing - 1)] = bottom;
+        }
+    };
+
+    // Every wavefront of the workgroup runs steps 0..sfinal (a uniform count,
+    // so all reach the same barriers); the result is read after the last step.
+    float y0 = yat(0), y1 = yat(1);
+    int s = 0;
+    for (; s + 2 <= sfinal + 1; s += 2) {
+        const float y2 = yat(s + 2), y3 = yat(s + 3);
+        if constexpr (EVENTS) ev.step<H>(s, x, xr, lane);
+        strip_step<ACC, H, PERCELL>(s - skew, y0, x, A, Bv, up_in, diag_in, rbase, band);
+        {
+            const T recv = lane_shift_down(Bv[H - 1], boundary(s + 1));
+            publish(s, Bv[H - 1]);
+            diag_in = up_in;
+            up_in = recv;
+        }
+        if constexpr (EVENTS) ev.step<H>(s + 1, x, xr, lane);
+        strip_step<ACC, H, PERCELL>(s + 1 - skew, y1, x, Bv, A, up_in, diag_in, rbase, band);
+        {
+            const T recv = lane_shift_down(A[H - 1], boundary(s + 2));
+            publish(s + 1, A[H - 1]);
+            diag_in = up_in;
+            up_in = recv;
+        }
+        y0 = y2;
+        y1 = y3;
+        if constexpr (G > 1) {
+            if ((s + 2) % kEpoch == 0) __syncthreads();
+        }
+    }
+    T res;
+    if (s <= sfinal) {  // one step left (s == sfinal)
+        if constexpr (EVENTS) ev.step<H>(s, x, xr, lane);
+        strip_step<ACC, H, PERCELL>(s - skew, y0, x, A, Bv, up_in, diag_in, rbase, band);
+        res = pick<H>(Bv, hf);
+    } else {
+        res = pick<H>(A, hf);
+    }
+    if (wave == wf && lane == lf) {
+        const int a = it.rows < it.cols ? it.rows : it.cols;
+        const int b = it.rows < it.cols ? it.cols : it.rows;
+        DI.out[condensed_index(a, b, DI.N)] = ACC::result(res);
+    }
+}
+
+template <class ACC, int H, int G, bool BANDED>
+__global__ __launch_bounds__(64 * G) void k_strip(const float *__restrict__ ws, const SeriesInfo *__restrict__ ser,
+                                                  const DatasetInfo *__restrict__ dsi,
+                                                  const WaveItem *__restrict__ items, unsigned *__restrict__ queue,
+                                                  unsigned n_items) {
+    __shared__ typename ACC::T ring[G > 1 ? G - 1 : 1][kRing];
+    __shared__ unsigned slot;
+    unsigned idx = blockIdx.x;
+    for (;;) {
+        if (queue) idx = next_item<G>(queue, &slot);
+        if (idx >= n_items) break;
+        strip_item<ACC, H, G, BANDED>(items[idx], ws, ser, dsi, ring);
+        if (!queue) break;
+    }
+}
+
+template <class ACC, int H, int G>
+hipError_t strip_launch(bool banded, const float *ws, const SeriesInfo *ser, const DatasetInfo *dsi,
+                        const WaveItem *items, unsigned n, unsigned *queue, unsigned grid, hipStream_t st) {
+    const dim3 g(grid), block(64 * G);
+    if (banded)
+        hipLaunchKernelGGL((k_strip<ACC, H, G, true>), g, block, 0, st, ws, ser, dsi, items, queue, n);
+    else
+        hipLaunchKernelGGL((k_strip<ACC, H, G, false>), g, block, 0, st, ws, ser, dsi, items, queue, n);
+    return hipGetLastError();
+}
+
+template <class ACC, int H, int G>
+int strip_slots(bool banded) {
+    return banded ? resident_blocks(reinterpret_cast<const void *>(&k_strip<ACC, H, G, true>), 64 * G)
+                  : resident_blocks(reinterpret_cast<const void *>(&k_strip<ACC, H, G, false>), 64 * G);
+}
+
+using StripFn = hipError_t (*)(bool, const float *, const SeriesInfo *, const DatasetInfo *, const WaveItem *,
+                               unsigned, unsigned *, unsigned, hipStream_t);
+using StripSlotsFn = int (*)(bool);
+struct StripEntry {
+    int accum, H, G;
+    StripFn fn;
+    StripSlotsFn slots;
+};
+
+#define DTWMI_STRIP(A, ACC, H, G) {A, H, G, &strip_launch<ACC, H, G>, &strip_slots<ACC, H, G>}
+// Instantiated shapes, per accumulation mode in increasing row capacity 64*H*G.
+const StripEntry kStrips[] = {
+    DTWMI_STRIP(0, AccPlain, 1, 1),  DTWMI_STRIP(0, AccPlain, 2, 1),  DTWMI_STRIP(0, AccPlain, 4, 1),
+    DTWMI_STRIP(0, AccPlain, 8, 1),  DTWMI_STRIP(0, AccPlain, 12, 1), DTWMI_STRIP(0, AccPlain, 16, 1),
+    DTWMI_STRIP(0, AccPlain, 24, 1), DTWMI_STRIP(0, AccPlain, 32, 1), DTWMI_STRIP(0, AccPlain, 16, 2),
+    DTWMI_STRIP(0, AccPlain, 48, 1), DTWMI_STRIP(0, AccPlain, 24, 2), DTWMI_STRIP(0, AccPlain, 64, 1),
+    DTWMI_STRIP(0, AccPlain, 32, 2), DTWMI_STRIP(0, AccPlain, 32, 4), DTWMI_STRIP(0, AccPlain, 32, 8),
+    DTWMI_STRIP(0, AccPlain, 64, 8),
+    DTWMI_STRIP(1, AccKahan, 1, 1),  DTWMI_STRIP(1, AccKahan, 2, 1),  DTWMI_STRIP(1, AccKahan, 4, 1),
+    DTWMI_STRIP(1, AccKahan, 8, 1),  DTWMI_STRIP(1, AccKahan, 16, 1), DTWMI_STRIP(1, AccKahan, 16, 2),
+    DTWMI_STRIP(1, AccKahan, 16, 4), DTWMI_STRIP(1, AccKahan, 16, 8), DTWMI_STRIP(1, AccKahan, 16, 16),
+    DTWMI_STRIP(2, AccF64, 1, 1),    DTWMI_STRIP(2, AccF64, 2, 1),    DTWMI_STRIP(2, AccF64, 4, 1),
+    DTWMI_STRIP(2, AccF64, 8, 1),    DTWMI_STRIP(2, AccF64, 16, 1),   DTWMI_STRIP(2, AccF64, 16, 2),
+    DTWMI_STRIP(2, AccF64, 16, 4),   DTWMI_STRIP(2, AccF64, 16, 8),   DTWMI_STRIP(2, AccF64, 16, 16),
+};
+#undef DTWMI_STRIP
+
+// Grid of a launch: one workgroup per item, or with a queue the resident
+// workgroups (at most one per item).
+unsigned grid_for(unsigned n, unsigned *queue, int slots) {
+    if (!queue || slots <= 0) return n;
+    return n < static_cast<unsigned>(slots) ? n : static_cast<unsigned>(slots);
+}
+
+}  // namespace
+
+int strip_shapes(int accum, StripShape *out, int max_out) {
+    int k = 0;
+    for (const StripEntry &e : kStrips)
+        if (e.accum == accum) {
+            if (out && k < max_out) out[k] = StripShape{e.H, e.G};
+            ++k;
+        }
+    return k;
+}
+
+int strip_resident(int accum, StripShape shape, bool banded) {
+    for (const StripEntry &e : kStrips)
+        if (e.accum == accum && e.H == shape.H && e.G == shape.G) return e.slots(banded);
+    return 0;
+}
+
+hipError_t launch_strip(int accum, StripShape shape, bool banded, const float *ws, const SeriesInfo *ser,
+                        const DatasetInfo *dsi, const WaveItem *items, unsigned n_items, unsigned *queue, int slots,
+                        hipStream_t stream) {
+    if (n_items == 0) return hipSuccess;
+    for (const StripEntry &e : kStrips)
+        if (e.accum == accum && e.H == shape.H && e.G == shape.G)
+            return e.fn(banded, ws, ser, dsi, items, n_items, queue, grid_for(n_items, queue, slots), stream);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace dtwmi
