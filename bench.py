@@ -30,6 +30,17 @@ if ROOT not in sys.path:
 # lane-operations (one FMA, min3 or sub = 1 op) it is 78.64 T op/s.
 PEAK_LANE_OPS_T = 256 * 128 * 2.4e9 / 1e12          # 78.64
 OPS_PER_CELL = 3
+# Per accumulation mode: VALU lane-operations of the recurrence per admissible
+# cell and the peak they run against.
+#   plain: v_sub, v_min3, v_fma (the square fused into the add)
+#   kahan: sub, mul, min3, two compares and two selects picking the carried
+#          compensation, then Kahan's add: sub, add, sub, sub  (11)
+#   fp64:  sub, mul, min, min, add in FP64 (5), against the FP64 vector peak
+#          78.6 TFLOP/s = 39.32 T lane-ops/s (an FMA counted as one op)
+PEAK_FP64_LANE_OPS_T = 78.6 / 2
+MODE_OPS = {"plain": (3, PEAK_LANE_OPS_T, "TOP/s (FP32 VALU lane-ops)"),
+            "kahan": (11, PEAK_LANE_OPS_T, "TOP/s (FP32 VALU lane-ops)"),
+            "fp64": (5, PEAK_FP64_LANE_OPS_T, "TOP/s (FP64 VALU lane-ops)")}
 # profile summary (profiles/<label>*.md) holding the counter-based HBM traffic of a workload's DP kernel
 PROFILE_LABELS = {("c2", "auto", "plain", "f32"): "lane_band_W103_c2"}
 
@@ -229,7 +240,8 @@ def main(argv=None):
 
     cells = info["band_cells"]
     value = cells / (ms_per_step * 1e-3) / 1e9
-    achieved = OPS_PER_CELL * cells / (k_avg * 1e-3) / 1e12
+    ops_cell, peak, peak_unit = MODE_OPS[args.accum]
+    achieved = ops_cell * cells / (k_avg * 1e-3) / 1e12
     line = {
         "metric": "DTW cell updates/s (GCUPS) for all-pairs matrix; % of FP32 VALU peak",
         "value": round(value, 2),
@@ -257,11 +269,12 @@ def main(argv=None):
         "roofline": {
             "bound": "alu",
             "achieved": round(achieved, 3),
-            "peak": round(PEAK_LANE_OPS_T, 2),
-            "unit": "TOP/s (FP32 VALU lane-ops)",
-            "frac": round(achieved / PEAK_LANE_OPS_T, 4),
+            "peak": round(peak, 2),
+            "unit": peak_unit,
+            "frac": round(achieved / peak, 4),
             "kernel_ms": round(k_avg, 4),
-            "ops_per_launch": OPS_PER_CELL * cells,
+            "ops_per_cell": ops_cell,
+            "ops_per_launch": ops_cell * cells,
             "traffic": recorded_traffic(PROFILE_LABELS.get((args.workload, args.kernel, args.accum, args.dtype), "-")),
         },
         "wall_s": round(wall, 3),
