@@ -91,12 +91,12 @@ __device__ __forceinline__ KahanCell lane_shift_down(KahanCell v, KahanCell fill
 // by 1e30 (its local cost overflows), so the cell loop itself carries no test.
 struct BandEvents {
     RowCounter en, ex;
-    int nloc, col_shift;  // rows of the pair from this wavefront's first row; column = s - l - col_shift
+    int col_shift;  // column of lane l at step s = s - l - col_shift
 
     template <int H>
     __device__ __forceinline__ void init(int band, int n_rows, int wave, int D) {
         const int row0 = wave * 64 * H;
-        nloc = n_rows - row0;
+        (void)n_rows;
         col_shift = wave * (64 + D);
         const int shift = row0 + col_shift;
         en.init<H>(band - shift);       // entry at step s: s + b - shift = l(H+1) + h
@@ -104,17 +104,26 @@ struct BandEvents {
     }
 
     // Apply the events of step s (counters are at step s on entry), then advance.
+    // Only the slot h == H (no row) needs a test.  An event whose lane q is
+    // outside 0..63 matches no lane; entries at columns <= 0 repeat the
+    // start-up value; events of rows past n touch cells that never feed row
+    // n-1.  Each move is a one-lane branch; the empty asm statement keeps the
+    // compiler from turning it into a select of the whole register vector.
     template <int H>
     __device__ __forceinline__ void step(int s, typename XVec<H>::T &xe, const typename XVec<H>::T &xr, int lane) {
-        if (en.h < H && en.q >= 0 && en.q < 64 && en.q * H + en.h < nloc && s - en.q - col_shift > 0) {
-            const float cur = xe[en.h];
-            const float v = xr[en.h];
-            xe[en.h] = lane == en.q ? v : cur;
+        (void)s;
+        if (en.h < H) {
+            if (lane == en.q) {
+                asm volatile("");
+                xe[en.h] = xr[en.h];
+            }
         }
         en.advance<H>();
-        if (ex.h < H && ex.q >= 0 && ex.q < 64 && ex.q * H + ex.h < nloc) {
-            const float cur = xe[ex.h];
-            xe[ex.h] = lane == ex.q ? kBig : cur;
+        if (ex.h < H) {
+            if (lane == ex.q) {
+                asm volatile("");
+                xe[ex.h] = kBig;
+            }
         }
         ex.advance<H>();
     }
