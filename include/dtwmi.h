@@ -168,6 +168,32 @@ int dtw_plan_describe(dtw_plan plan, char *buf, int64_t size, int64_t *needed);
 
 int dtw_plan_destroy(dtw_plan plan);
 
+/*
+ * Pair subsets.  Some uses need only some distances: k-medoids evaluates each
+ * series against the current medoids, not every pair (the paper's clustering
+ * section).  A pair list names series of one dataset; i == j is allowed (its
+ * cost is 0) and a pair may appear several times.
+ */
+typedef struct dtw_pair {
+    int32_t i, j; /* series indices, 0 <= i, j < N */
+} dtw_pair;
+
+/*
+ * Plan for a pair list of one dataset: out (device, n_pairs floats) receives
+ * out[k] = DTW(series pairs[k].i, series pairs[k].j) at every execute.
+ * ds->out_condensed is ignored (may be NULL).  pairs (host) is copied and may
+ * be freed after the call; ds->series and out stay owned by the caller and
+ * must stay alive until dtw_plan_destroy.  Pairs of an equal-length dataset
+ * with 2*w+1 <= 127 (PLAIN) run on the lane-band kernel in tiles of 64 pairs
+ * that share a series (the series named most often in the list); all others
+ * on the wavefront kernels.  Indices outside 0..N-1 return DTW_ERR_INVALID_ARG.
+ */
+int dtw_plan_create_pairs(dtw_plan *plan, const dtw_dataset *ds, const dtw_pair *pairs, int64_t n_pairs,
+                          float *out, const dtw_options *opt);
+
+/* Blocking form of a pair-list plan: create, execute on opt->stream, synchronise, destroy. */
+int dtw_pairs(const dtw_dataset *ds, const dtw_pair *pairs, int64_t n_pairs, float *out, const dtw_options *opt);
+
 /* Admissible cells of one n x m problem under window w (host arithmetic only). */
 int dtw_band_cells(int32_t n, int32_t m, int32_t window, int64_t *cells);
 

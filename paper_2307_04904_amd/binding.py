@@ -24,6 +24,7 @@ DTW_FLAG_AUTOTUNE = 4
 
 EXPORTED = ["dtw_pairwise", "dtw_pairwise_ex", "dtw_plan_create", "dtw_plan_execute",
             "dtw_plan_last_kernel_ms", "dtw_plan_info", "dtw_plan_describe", "dtw_plan_destroy", "dtw_band_cells",
+            "dtw_plan_create_pairs", "dtw_pairs",
             "dtw_last_error", "dtw_version"]
 
 
@@ -42,6 +43,10 @@ class dtw_dataset(ctypes.Structure):
 class dtw_options(ctypes.Structure):
     _fields_ = [("dtype", ctypes.c_int32), ("accum", ctypes.c_int32), ("kernel", ctypes.c_int32),
                 ("flags", ctypes.c_int32), ("rows_per_lane", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+
+
+class dtw_pair(ctypes.Structure):
+    _fields_ = [("i", ctypes.c_int32), ("j", ctypes.c_int32)]
 
 
 class dtw_plan_stats(ctypes.Structure):
@@ -214,6 +219,40 @@ class Plan:
             pass
 
 
+def _pair_array(pairs):
+    """(P, 2) integer pairs as a contiguous int32 array usable as dtw_pair[P]."""
+    a = np.ascontiguousarray(np.asarray(pairs, dtype=np.int32).reshape(-1, 2))
+    return a, a.ctypes.data_as(ctypes.POINTER(dtw_pair))
+
+
+def dtw_pairs(series, lengths, offsets, window, pairs, out, dtype="f32", accum="plain", kernel="auto",
+              stream=None, queue=True):
+    """Blocking pair-list evaluation: out[k] = DTW(series pairs[k][0], series pairs[k][1])."""
+    d, keep = _make_dataset(series, lengths, offsets, window, None)
+    arr, ptr = _pair_array(pairs)
+    o = _options(dtype, accum, kernel, 0 if queue else DTW_FLAG_NO_QUEUE, stream)
+    _check(load().dtw_pairs(ctypes.byref(d), ptr, ctypes.c_int64(len(arr)),
+                            ctypes.c_void_p(out.data_ptr() if out is not None else 0), ctypes.byref(o)))
+    del keep
+
+
+class PairPlan(Plan):
+    """dtw_plan_create_pairs: a plan over an explicit pair list of one dataset."""
+
+    def __init__(self, series, lengths, offsets, window, pairs, out, dtype="f32", accum="plain", kernel="auto",
+                 timing=False, queue=True, autotune=False):
+        self._lib = load()
+        d, keep = _make_dataset(series, lengths, offsets, window, None)
+        arr, ptr = _pair_array(pairs)
+        self._keep = [(keep, series, out, arr)]
+        flags = ((DTW_FLAG_TIMING if timing else 0) | (0 if queue else DTW_FLAG_NO_QUEUE)
+                 | (DTW_FLAG_AUTOTUNE if autotune else 0))
+        o = _options(dtype, accum, kernel, flags, False)
+        self._h = ctypes.c_void_p()
+        _check(self._lib.dtw_plan_create_pairs(ctypes.byref(self._h), ctypes.byref(d), ptr, ctypes.c_int64(len(arr)),
+                                               ctypes.c_void_p(out.data_ptr()), ctypes.byref(o)))
+
+
 def device_series(ds, device="cuda"):
     """Upload a synth.Dataset's stored values as a torch tensor (bf16 kept as raw 16-bit words)."""
     import torch
@@ -225,6 +264,15 @@ def device_series(ds, device="cuda"):
     else:
         t = torch.from_numpy(np.ascontiguousarray(v, dtype=np.float32))
     return t.to(device)
+
+
+def pairs_of(ds, pairs, accum="plain", kernel="auto", device="cuda"):
+    """DTW of listed pairs of a synth.Dataset on the GPU, as a torch tensor (blocking)."""
+    import torch
+    series = device_series(ds, device)
+    out = torch.full((max(1, len(pairs)),), float("nan"), dtype=torch.float32, device=device)
+    dtw_pairs(series, ds.lengths, ds.offsets, ds.window, pairs, out, dtype=ds.dtype, accum=accum, kernel=kernel)
+    return out[:len(pairs)]
 
 
 def pairwise(ds, accum="plain", kernel="auto", device="cuda", out=None, rows_per_lane=0, queue=True):

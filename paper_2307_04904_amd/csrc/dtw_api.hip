@@ -70,6 +70,12 @@ int64_t band_cells(int64_t n, int64_t m, int64_t b) {
     return upper - lower;
 }
 
+// Condensed index of the unordered pair {i, j}, i != j.
+int64_t condensed_host(int32_t i, int32_t j, int32_t N) {
+    const int64_t a = std::min(i, j), b = std::max(i, j);
+    return a * N - a * (a + 1) / 2 + (b - a - 1);
+}
+
 int64_t effective_band(int32_t w, int32_t n, int32_t m) {
     if (w < 0) return -1;
     const int64_t d = n > m ? (int64_t)n - m : (int64_t)m - n;
@@ -199,7 +205,8 @@ int max_strip_rows(int accum) {
 // A pair for the wavefront families: `shorter` has n points, `longer` m >= n.
 struct WavePair {
     int32_t d, shorter, longer, n, m;
-    int32_t b;  // effective band, -1 = none
+    int32_t b;     // effective band, -1 = none
+    int64_t slot;  // output index in the dataset's output
 };
 
 // Kernel instance of a wavefront pair: a strip shape, or (G == 0) the cyclic
@@ -236,7 +243,8 @@ Choice model_choice(int accum, int kernel, int force_h, const WavePair &w) {
 // Work item of a pair for its kernel: strips spread the shorter series over
 // the lanes, the cyclic kernel the longer one.
 WaveItem make_item(Choice c, const WavePair &w) {
-    return c.cyclic() ? WaveItem{w.d, w.longer, w.shorter, w.b} : WaveItem{w.d, w.shorter, w.longer, w.b};
+    return c.cyclic() ? WaveItem{w.d, w.longer, w.shorter, w.b, w.slot}
+                      : WaveItem{w.d, w.shorter, w.longer, w.b, w.slot};
 }
 
 // Half-octave bucket of a positive length: 2*floor(log2 v) + (v >= 1.5 * 2^floor(log2 v)).
@@ -268,6 +276,7 @@ struct dtw_plan_s {
     SeriesInfo *d_ser = nullptr;
     DatasetInfo *d_ds = nullptr;
     LaneItem *d_lane = nullptr;
+    LanePartner *d_partner = nullptr;
     WaveItem *d_wave = nullptr;
     unsigned *d_queue = nullptr;  // one counter per wavefront group, zeroed by every execute
     int n_queue = 0;
@@ -297,11 +306,13 @@ int validate_options(const dtw_options *opt) {
     return DTW_OK;
 }
 
-int validate_dataset(const dtw_dataset &d, int idx) {
+// need_all: the dataset is evaluated for all its pairs (N >= 2 needs series
+// and out_condensed); otherwise for a pair list (N >= 1 needs series).
+int validate_dataset(const dtw_dataset &d, int idx, bool need_all = true) {
     if (d.N < 0) return fail(DTW_ERR_INVALID_ARG, "dataset %d: N=%d < 0", idx, d.N);
-    if (d.N < 2) return DTW_OK;
+    if (d.N < (need_all ? 2 : 1)) return DTW_OK;
     if (!d.series) return fail(DTW_ERR_INVALID_ARG, "dataset %d: series is NULL", idx);
-    if (!d.out_condensed) return fail(DTW_ERR_INVALID_ARG, "dataset %d: out_condensed is NULL", idx);
+    if (need_all && !d.out_condensed) return fail(DTW_ERR_INVALID_ARG, "dataset %d: out_condensed is NULL", idx);
     if (!d.lengths || !d.offsets) return fail(DTW_ERR_INVALID_ARG, "dataset %d: lengths/offsets is NULL", idx);
     for (int32_t s = 0; s < d.N; ++s) {
         if (d.lengths[s] < 1) return fail(DTW_ERR_INVALID_ARG, "dataset %d: lengths[%d]=%d < 1", idx, s, d.lengths[s]);
@@ -474,16 +485,22 @@ int dtw_band_cells(int32_t n, int32_t m, int32_t window, int64_t *cells) {
     return DTW_OK;
 }
 
-int dtw_plan_create(dtw_plan *plan_out, const dtw_dataset *ds, int32_t n_datasets, const dtw_options *opt) {
-    g_err.clear();
-    if (!plan_out) return fail(DTW_ERR_INVALID_ARG, "plan is NULL");
-    *plan_out = nullptr;
-    if (n_datasets < 0) return fail(DTW_ERR_INVALID_ARG, "n_datasets=%d < 0", n_datasets);
-    if (n_datasets > 0 && !ds) return fail(DTW_ERR_INVALID_ARG, "datasets is NULL");
-    int rc = validate_options(opt);
-    if (rc) return rc;
-    for (int32_t d = 0; d < n_datasets; ++d)
-        if ((rc = validate_dataset(ds[d], d))) return rc;
+}  // extern "C"
+
+namespace {
+
+// An explicit pair list for dataset 0 (dtw_plan_create_pairs).
+struct PairRequest {
+    const dtw_pair *pairs;
+    int64_t n;
+    float *out;
+};
+
+// Plan for all pairs of every dataset (req == nullptr) or for the listed
+// pairs of dataset 0.  Arguments are validated by the callers.
+int plan_build(dtw_plan *plan_out, const dtw_dataset *ds, int32_t n_datasets, const dtw_options *opt,
+               const PairRequest *req) {
+    int rc = DTW_OK;
 
     const int dtype = opt ? opt->dtype : DTW_F32;
     const int accum = opt ? opt->accum : DTW_ACC_PLAIN;
@@ -496,6 +513,7 @@ int dtw_plan_create(dtw_plan *plan_out, const dtw_dataset *ds, int32_t n_dataset
     std::vector<SeriesInfo> ser;
     std::vector<DatasetInfo> dsi;
     std::vector<LaneItem> lane_items;
+    std::vector<LanePartner> partners;  // explicit partners of pair-list lane items
     std::map<int, std::vector<LaneItem>> lane_by_w;
     std::vector<WavePair> wpairs;
     dtw_plan_stats st{};
@@ -504,11 +522,11 @@ int dtw_plan_create(dtw_plan *plan_out, const dtw_dataset *ds, int32_t n_dataset
     for (int32_t d = 0; d < n_datasets; ++d) {
         const dtw_dataset &D = ds[d];
         DatasetInfo info{};
-        info.out = D.out_condensed;
+        info.out = req ? req->out : D.out_condensed;
         info.N = D.N;
         info.window = D.window;
         info.series_base = static_cast<int32_t>(ser.size());
-        if (D.N < 2) {
+        if (D.N < (req ? 1 : 2) || (req && req->n == 0)) {
             info.L = -1;
             dsi.push_back(info);
             continue;
@@ -526,7 +544,7 @@ int dtw_plan_create(dtw_plan *plan_out, const dtw_dataset *ds, int32_t n_dataset
         }
         info.L = uniform ? D.lengths[0] : -1;
         dsi.push_back(info);
-        const int64_t npairs = (int64_t)D.N * (D.N - 1) / 2;
+        const int64_t npairs = req ? req->n : (int64_t)D.N * (D.N - 1) / 2;
         st.pairs += npairs;
 
         // Kernel family for this dataset.
@@ -542,7 +560,32 @@ int dtw_plan_create(dtw_plan *plan_out, const dtw_dataset *ds, int32_t n_dataset
                         d, kLaneMaxW);
         if (kernel == DTW_KERNEL_WAVE || kernel == DTW_KERNEL_CYCLIC) lane_w = 0;
 
-        if (lane_w) {
+        if (lane_w && req) {
+            // Each listed pair goes to the tile of whichever of its series is
+            // named more often in the list (the shared column series of a
+            // wavefront), in runs of 64 partners: every series against a few
+            // medoids makes full tiles around each medoid.
+            const int32_t L = D.lengths[0], b = (lane_w - 1) / 2;
+            st.band_cells += npairs * band_cells(L, L, b >= L - 1 ? -1 : b);
+            std::vector<int64_t> count(D.N, 0);
+            for (int64_t k = 0; k < req->n; ++k) {
+                ++count[req->pairs[k].i];
+                ++count[req->pairs[k].j];
+            }
+            std::map<int32_t, std::vector<LanePartner>> by_a;
+            for (int64_t k = 0; k < req->n; ++k) {
+                const int32_t i = req->pairs[k].i, j = req->pairs[k].j;
+                const bool on_i = count[i] > count[j] || (count[i] == count[j] && i <= j);
+                by_a[on_i ? i : j].push_back(LanePartner{on_i ? j : i, 0, k});
+            }
+            for (auto &kv : by_a)
+                for (size_t s0 = 0; s0 < kv.second.size(); s0 += 64) {
+                    const int32_t cnt = (int32_t)std::min<size_t>(64, kv.second.size() - s0);
+                    lane_by_w[lane_w].push_back(LaneItem{d, kv.first, 0, cnt, (int64_t)partners.size()});
+                    partners.insert(partners.end(), kv.second.begin() + s0, kv.second.begin() + s0 + cnt);
+                    st.computed_cells += (int64_t)64 * L * lane_w;
+                }
+        } else if (lane_w) {
             const int32_t N = D.N, L = D.lengths[0], b = (lane_w - 1) / 2;
             st.band_cells += npairs * band_cells(L, L, b >= L - 1 ? -1 : b);
             for (int32_t a = 0; a < N; ++a) {
@@ -550,16 +593,23 @@ int dtw_plan_create(dtw_plan *plan_out, const dtw_dataset *ds, int32_t n_dataset
                 if (N % 2 == 0 && a < N / 2) h = N / 2;
                 for (int32_t d0 = 1; d0 <= h; d0 += 64) {
                     const int32_t cnt = std::min(64, h - d0 + 1);
-                    lane_by_w[lane_w].push_back(LaneItem{d, a, d0, cnt});
+                    lane_by_w[lane_w].push_back(LaneItem{d, a, d0, cnt, -1});
                     st.computed_cells += (int64_t)64 * L * lane_w;
                 }
             }
         } else {
-            for (int32_t i = 0; i < D.N; ++i) {
-                for (int32_t j = i + 1; j < D.N; ++j) {
+            const int64_t n_list = req ? req->n : 0;
+            for (int64_t k = 0, i = 0, j = 1; req ? k < n_list : i < D.N - 1; ++k) {
+                if (req) {
+                    i = req->pairs[k].i;
+                    j = req->pairs[k].j;
+                }
+                {
                     const int32_t ni = D.lengths[i], nj = D.lengths[j];
                     const bool swap = nj < ni;
-                    WavePair w{d, swap ? j : i, swap ? i : j, std::min(ni, nj), std::max(ni, nj), 0};
+                    WavePair w{d, (int32_t)(swap ? j : i), (int32_t)(swap ? i : j), std::min(ni, nj),
+                               std::max(ni, nj), 0, 0};
+                    w.slot = req ? k : condensed_host((int32_t)i, (int32_t)j, D.N);
                     w.b = static_cast<int32_t>(effective_band(D.window, w.n, w.m));
                     st.band_cells += band_cells(w.n, w.m, w.b);
                     if (!model_choice(accum, kernel, force_h, w).H) {
@@ -567,12 +617,16 @@ int dtw_plan_create(dtw_plan *plan_out, const dtw_dataset *ds, int32_t n_dataset
                             return fail(DTW_ERR_UNSUPPORTED,
                                         "dataset %d: pair (%d,%d) (%d x %d points, band %d): no kernel with "
                                         "rows_per_lane=%d fits it",
-                                        d, i, j, w.n, w.m, w.b, force_h);
+                                        d, (int)i, (int)j, w.n, w.m, w.b, force_h);
                         return fail(DTW_ERR_UNSUPPORTED,
-                                    "dataset %d: pair (%d,%d) has both series longer than %d points", d, i, j,
-                                    max_strip_rows(accum));
+                                    "dataset %d: pair (%d,%d) has both series longer than %d points", d, (int)i,
+                                    (int)j, max_strip_rows(accum));
                     }
                     wpairs.push_back(w);
+                }
+                if (!req && ++j == D.N) {
+                    ++i;
+                    j = i + 1;
                 }
             }
         }
@@ -605,6 +659,8 @@ int dtw_plan_create(dtw_plan *plan_out, const dtw_dataset *ds, int32_t n_dataset
     off = align_up(off + dsi.size() * sizeof(DatasetInfo), 256);
     const size_t o_lane = off;
     off = align_up(off + lane_items.size() * sizeof(LaneItem), 256);
+    const size_t o_partner = off;
+    off = align_up(off + partners.size() * sizeof(LanePartner), 256);
     const size_t o_wave = off;
     off = align_up(off + wpairs.size() * sizeof(WaveItem), 256);
     const size_t o_queue = off;
@@ -628,6 +684,7 @@ int dtw_plan_create(dtw_plan *plan_out, const dtw_dataset *ds, int32_t n_dataset
     p->d_ser = reinterpret_cast<SeriesInfo *>(base + o_ser);
     p->d_ds = reinterpret_cast<DatasetInfo *>(base + o_ds);
     p->d_lane = reinterpret_cast<LaneItem *>(base + o_lane);
+    p->d_partner = reinterpret_cast<LanePartner *>(base + o_partner);
     p->d_wave = reinterpret_cast<WaveItem *>(base + o_wave);
     struct Up {
         void *dst;
@@ -636,7 +693,8 @@ int dtw_plan_create(dtw_plan *plan_out, const dtw_dataset *ds, int32_t n_dataset
     } ups[] = {{p->d_src, src.data(), src.size() * sizeof(SeriesSrc)},
                {p->d_ser, ser.data(), ser.size() * sizeof(SeriesInfo)},
                {p->d_ds, dsi.data(), dsi.size() * sizeof(DatasetInfo)},
-               {p->d_lane, lane_items.data(), lane_items.size() * sizeof(LaneItem)}};
+               {p->d_lane, lane_items.data(), lane_items.size() * sizeof(LaneItem)},
+               {p->d_partner, partners.data(), partners.size() * sizeof(LanePartner)}};
     for (const Up &u : ups) {
         if (!u.bytes) continue;
         e = hipMemcpy(u.dst, u.src, u.bytes, hipMemcpyHostToDevice);
@@ -724,6 +782,48 @@ int dtw_plan_create(dtw_plan *plan_out, const dtw_dataset *ds, int32_t n_dataset
     return DTW_OK;
 }
 
+int validate_pairs(const dtw_dataset *ds, const dtw_pair *pairs, int64_t n_pairs, const float *out) {
+    if (!ds) return fail(DTW_ERR_INVALID_ARG, "dataset is NULL");
+    if (n_pairs < 0) return fail(DTW_ERR_INVALID_ARG, "n_pairs=%lld < 0", (long long)n_pairs);
+    if (n_pairs == 0) return DTW_OK;
+    if (!pairs || !out) return fail(DTW_ERR_INVALID_ARG, "pairs or out is NULL");
+    int rc = validate_dataset(*ds, 0, false);
+    if (rc) return rc;
+    for (int64_t k = 0; k < n_pairs; ++k)
+        if (pairs[k].i < 0 || pairs[k].i >= ds->N || pairs[k].j < 0 || pairs[k].j >= ds->N)
+            return fail(DTW_ERR_INVALID_ARG, "pairs[%lld] = (%d, %d) outside 0..%d", (long long)k, pairs[k].i,
+                        pairs[k].j, ds->N - 1);
+    return DTW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dtw_plan_create(dtw_plan *plan_out, const dtw_dataset *ds, int32_t n_datasets, const dtw_options *opt) {
+    g_err.clear();
+    if (!plan_out) return fail(DTW_ERR_INVALID_ARG, "plan is NULL");
+    *plan_out = nullptr;
+    if (n_datasets < 0) return fail(DTW_ERR_INVALID_ARG, "n_datasets=%d < 0", n_datasets);
+    if (n_datasets > 0 && !ds) return fail(DTW_ERR_INVALID_ARG, "datasets is NULL");
+    int rc = validate_options(opt);
+    if (rc) return rc;
+    for (int32_t d = 0; d < n_datasets; ++d)
+        if ((rc = validate_dataset(ds[d], d))) return rc;
+    return plan_build(plan_out, ds, n_datasets, opt, nullptr);
+}
+
+int dtw_plan_create_pairs(dtw_plan *plan_out, const dtw_dataset *ds, const dtw_pair *pairs, int64_t n_pairs,
+                          float *out, const dtw_options *opt) {
+    g_err.clear();
+    if (!plan_out) return fail(DTW_ERR_INVALID_ARG, "plan is NULL");
+    *plan_out = nullptr;
+    int rc = validate_options(opt);
+    if (rc || (rc = validate_pairs(ds, pairs, n_pairs, out))) return rc;
+    const PairRequest req{pairs, n_pairs, out};
+    return plan_build(plan_out, ds, 1, opt, &req);
+}
+
 int dtw_plan_execute(dtw_plan p, void *stream) {
     if (!p) return fail(DTW_ERR_INVALID_ARG, "plan is NULL");
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -734,7 +834,7 @@ int dtw_plan_execute(dtw_plan p, void *stream) {
         return hip_fail(e, "queue reset kernel launch");
     int q = 0;  // queue counter of the next group
     for (const LaneGroup &g : p->lane_groups) {
-        e = launch_lane(g.W, p->ws, p->d_ser, p->d_ds, p->d_lane + g.begin, (unsigned)g.count, s);
+        e = launch_lane(g.W, p->ws, p->d_ser, p->d_ds, p->d_lane + g.begin, p->d_partner, (unsigned)g.count, s);
         if (e != hipSuccess) return hip_fail(e, "lane-band kernel launch");
     }
     for (const WaveGroup &g : p->wave_groups) {
@@ -842,6 +942,26 @@ int dtw_pairwise_ex(const dtw_dataset *ds, const dtw_options *opt) {
     o.flags &= DTW_FLAG_NO_QUEUE | DTW_FLAG_AUTOTUNE;  // timing needs the plan API
     dtw_plan p = nullptr;
     rc = dtw_plan_create(&p, ds, 1, &o);
+    if (rc) return rc;
+    rc = dtw_plan_execute(p, o.stream);
+    hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(o.stream));
+    destroy_plan(p);
+    if (rc) return rc;
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    return DTW_OK;
+}
+
+int dtw_pairs(const dtw_dataset *ds, const dtw_pair *pairs, int64_t n_pairs, float *out, const dtw_options *opt) {
+    g_err.clear();
+    int rc = validate_options(opt);
+    if (rc || (rc = validate_pairs(ds, pairs, n_pairs, out))) return rc;
+    if (n_pairs == 0) return DTW_OK;  // nothing to write, no HIP call
+    dtw_options o{};
+    if (opt) o = *opt;
+    o.flags &= DTW_FLAG_NO_QUEUE | DTW_FLAG_AUTOTUNE;  // timing needs the plan API
+    dtw_plan p = nullptr;
+    const PairRequest req{pairs, n_pairs, out};
+    rc = plan_build(&p, ds, 1, &o, &req);
     if (rc) return rc;
     rc = dtw_plan_execute(p, o.stream);
     hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(o.stream));

@@ -188,11 +188,7 @@ __device__ __forceinline__ void cyc_item(const WaveItem it, const float *__restr
     } else {
         res = pick<H>(A, hf);
     }
-    if (lane == (Qf & 63)) {
-        const int a = it.rows < it.cols ? it.rows : it.cols;
-        const int bb = it.rows < it.cols ? it.cols : it.rows;
-        DI.out[condensed_index(a, bb, DI.N)] = res;
-    }
+    if (lane == (Qf & 63)) DI.out[it.slot] = res;
 }
 
 template <int H>

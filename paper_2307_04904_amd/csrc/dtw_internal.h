@@ -37,16 +37,26 @@ struct DatasetInfo {
     int32_t series_base;  // global index of the dataset's first series
 };
 
-// Lane-band work item: one wavefront evaluates the pairs
-// (a, (a + d0 + lane) mod N) for lane < cnt, all series of length L.
+// Lane-band work item: one wavefront evaluates, for lane < cnt, the pair of
+// series a and partner b written to output slot k:
+//   list < 0:  b = (a + d0 + lane) mod N, k = condensed index of (a, b);
+//   list >= 0: (b, k) = partners[list + lane] (explicit pair lists).
+// All series of the dataset have length L.
 struct LaneItem {
     int32_t ds, a, d0, cnt;
+    int64_t list;
+};
+struct LanePartner {
+    int32_t b, pad_;
+    int64_t slot;
 };
 
-// Wavefront work item: one wavefront evaluates one pair; `rows` is the series
-// spread over the lanes (the shorter one), `cols` the one swept step by step.
+// Wavefront work item: one pair; `rows` is the series spread over the lanes,
+// `cols` the one swept step by step; the result goes to out[slot] of the
+// dataset (the condensed index for all-pairs plans).
 struct WaveItem {
     int32_t ds, rows, cols, band;  // band = max(w, |n-m|), or -1 for none
+    int64_t slot;
 };
 
 // Kernel launchers (dtw_kernels.hip).  All asynchronous on `stream`.
@@ -64,7 +74,7 @@ int resident_blocks(const void *fn, int block);
 bool lane_width_supported(int W);
 // Lane-band items all cost the same: one workgroup per item, no queue.
 hipError_t launch_lane(int W, const float *ws, const SeriesInfo *ser, const DatasetInfo *dsi,
-                       const LaneItem *items, unsigned n_items, hipStream_t stream);
+                       const LaneItem *items, const LanePartner *partners, unsigned n_items, hipStream_t stream);
 // Strip shapes of the wavefront kernels: H rows per lane, G wavefronts per pair
 // (a workgroup of 64*G lanes covers up to 64*H*G rows of the shorter series).
 struct StripShape {

@@ -94,14 +94,25 @@ __device__ __forceinline__ void lane_group(float (&st)[W], const float (&x)[R], 
 template <int W>
 __global__ __launch_bounds__(64) void k_lane(const float *__restrict__ ws, const SeriesInfo *__restrict__ ser,
                                              const DatasetInfo *__restrict__ dsi,
-                                             const LaneItem *__restrict__ items) {
+                                             const LaneItem *__restrict__ items,
+                                             const LanePartner *__restrict__ partners) {
     constexpr int B = (W - 1) / 2, R = kLaneRows, C = kLaneChunk;
     const LaneItem it = items[blockIdx.x];
     const DatasetInfo D = dsi[it.ds];
     const int lane = threadIdx.x;
     const bool valid = lane < it.cnt;
-    int bl = it.a + it.d0 + lane;
-    bl = bl >= D.N ? bl - D.N : bl;
+    int bl;
+    int64_t slot;
+    if (it.list < 0) {  // all pairs: cyclic partner tiling, condensed output
+        bl = it.a + it.d0 + lane;
+        bl = bl >= D.N ? bl - D.N : bl;
+        const int a = it.a < bl ? it.a : bl, b = it.a < bl ? bl : it.a;
+        slot = condensed_index(a, b, D.N);
+    } else {  // explicit pair list
+        const LanePartner P = partners[it.list + (valid ? lane : 0)];
+        bl = P.b;
+        slot = P.slot;
+    }
     if (!valid) bl = it.a;  // idle lanes recompute a valid pair and store nothing
     const float *__restrict__ ycol = ws + ser[D.series_base + it.a].pstart - B;  // ycol[v] = y[v-B]
     const float *__restrict__ xrow = ws + ser[D.series_base + bl].pstart;
@@ -139,20 +150,17 @@ __global__ __launch_bounds__(64) void k_lane(const float *__restrict__ ws, const
         }
     }
 
-    if (valid) {
-        const int a = it.a < bl ? it.a : bl, b = it.a < bl ? bl : it.a;
-        D.out[condensed_index(a, b, D.N)] = st[B];
-    }
+    if (valid) D.out[slot] = st[B];
 }
 
 
-using LaneFn = hipError_t (*)(const float *, const SeriesInfo *, const DatasetInfo *, const LaneItem *, unsigned,
-                              hipStream_t);
+using LaneFn = hipError_t (*)(const float *, const SeriesInfo *, const DatasetInfo *, const LaneItem *,
+                              const LanePartner *, unsigned, hipStream_t);
 
 template <int I>
 hipError_t lane_launcher(const float *ws, const SeriesInfo *ser, const DatasetInfo *dsi, const LaneItem *items,
-                         unsigned n, hipStream_t st) {
-    hipLaunchKernelGGL(k_lane<2 * I + 1>, dim3(n), dim3(64), 0, st, ws, ser, dsi, items);
+                         const LanePartner *partners, unsigned n, hipStream_t st) {
+    hipLaunchKernelGGL(k_lane<2 * I + 1>, dim3(n), dim3(64), 0, st, ws, ser, dsi, items, partners);
     return hipGetLastError();
 }
 
@@ -169,10 +177,10 @@ const std::array<LaneFn, (kLaneMaxW + 1) / 2> kLaneTable =
 bool lane_width_supported(int W) { return W >= 1 && W <= kLaneMaxW && (W & 1); }
 
 hipError_t launch_lane(int W, const float *ws, const SeriesInfo *ser, const DatasetInfo *dsi,
-                       const LaneItem *items, unsigned n_items, hipStream_t stream) {
+                       const LaneItem *items, const LanePartner *partners, unsigned n_items, hipStream_t stream) {
     if (!lane_width_supported(W)) return hipErrorInvalidValue;
     if (n_items == 0) return hipSuccess;
-    return kLaneTable[(W - 1) / 2](ws, ser, dsi, items, n_items, stream);
+    return kLaneTable[(W - 1) / 2](ws, ser, dsi, items, partners, n_items, stream);
 }
 
 }  // namespace dtwmi

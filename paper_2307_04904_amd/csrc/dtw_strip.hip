@@ -261,11 +261,7 @@ __device__ __forceinline__ void strip_item(const WaveItem it, const float *__res
     } else {
         res = pick<H>(A, hf);
     }
-    if (wave == wf && lane == lf) {
-        const int a = it.rows < it.cols ? it.rows : it.cols;
-        const int b = it.rows < it.cols ? it.cols : it.rows;
-        DI.out[condensed_index(a, b, DI.N)] = ACC::result(res);
-    }
+    if (wave == wf && lane == lf) DI.out[it.slot] = ACC::result(res);
 }
 
 template <class ACC, int H, int G, bool BANDED>

@@ -91,6 +91,32 @@ def test_invalid_arguments_rejected_on_host():
     assert _call_ex(ok_len, ok_off, flags=16)[0] == B.DTW_ERR_INVALID_ARG
 
 
+def _call_pairs(pairs, N=4, out=FAKE_DEV, series=FAKE_DEV):
+    lib = B.load()
+    ln = np.full(N, 5, dtype=np.int32)
+    off = np.arange(N, dtype=np.int64) * 5
+    d = B.dtw_dataset()
+    d.series = ctypes.c_void_p(series)
+    d.lengths = ln.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    d.offsets = off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    d.N, d.window, d.out_condensed = N, -1, None
+    arr = np.ascontiguousarray(np.asarray(pairs, dtype=np.int32).reshape(-1, 2))
+    ptr = arr.ctypes.data_as(ctypes.POINTER(B.dtw_pair)) if len(arr) else None
+    rc = lib.dtw_pairs(ctypes.byref(d), ptr, ctypes.c_int64(len(arr)), ctypes.c_void_p(out), None)
+    return rc, B.dtw_last_error()
+
+
+def test_pair_list_validation_on_host():
+    assert _call_pairs([])[0] == B.DTW_OK  # nothing to do, no HIP call
+    rc, msg = _call_pairs([[0, 1], [2, 4]])
+    assert rc == B.DTW_ERR_INVALID_ARG and "pairs[1]" in msg
+    assert _call_pairs([[0, -1]])[0] == B.DTW_ERR_INVALID_ARG
+    assert _call_pairs([[0, 1]], out=0)[0] == B.DTW_ERR_INVALID_ARG
+    assert _call_pairs([[0, 1]], series=0)[0] == B.DTW_ERR_INVALID_ARG
+    lib = B.load()
+    assert lib.dtw_plan_create_pairs(None, None, None, ctypes.c_int64(0), None, None) == B.DTW_ERR_INVALID_ARG
+
+
 def test_fewer_than_two_series_is_a_no_op():
     # no HIP call is made: this passes on a machine without a GPU
     assert _call_ex([], [], series=0, out=0)[0] == B.DTW_OK

@@ -360,6 +360,58 @@ def test_wave_kernel_forced_rows_per_lane(H):
     assert np.array_equal(run(ds, kernel="wave", rows_per_lane=H), run(ds, kernel="wave"))
 
 
+# ---------------------------------------------------------------- pair lists
+
+def _random_pairs(rng, N, P):
+    i = rng.integers(0, N, size=P)
+    j = rng.integers(0, N, size=P)
+    pairs = np.stack([i, j], axis=1).astype(np.int32)
+    pairs[:3] = [[0, 0], [N - 1, 0], [0, N - 1]]  # a self pair and one pair in both orders
+    pairs[3] = pairs[4]                          # a duplicate
+    return pairs
+
+
+@pytest.mark.parametrize("window", [-1, 9, 60])
+def test_pair_list_ragged_lengths(window):
+    # wavefront kernels (strip and cyclic) on an explicit, unordered pair list
+    B = _gpu()
+    ds = synth.small_random(seed=700 + max(window, 0), N=60, len_lo=20, len_hi=900, window=window)
+    pairs = _random_pairs(np.random.default_rng(1), ds.N, 700)
+    got = B.pairs_of(ds, pairs).cpu().numpy()
+    ref = oracle_pairs(ds, pairs[:, 0], pairs[:, 1])
+    assert_close(got, ref, what="pair list w=%d" % window)
+    assert got[0] == 0.0 and got[1] == got[2] and got[3] == got[4]
+
+
+def test_pair_list_medoids_on_lane_kernel():
+    # every series against 5 medoids: tiles of 64 partners around each medoid on
+    # the lane-band kernel, bit for bit the values of the all-pairs plan
+    from paper_2307_04904_amd import binding as B
+    _gpu()
+    ds = synth.small_random(seed=71, N=300, len_lo=96, len_hi=96, window=12)
+    medoids = [3, 77, 150, 151, 299]
+    pairs = np.array([[i, m] for m in medoids for i in range(ds.N)], dtype=np.int32)
+    series = B.device_series(ds)
+    out = torch.full((len(pairs),), float("nan"), device="cuda")
+    plan = B.PairPlan(series, ds.lengths, ds.offsets, ds.window, pairs, out, timing=True)
+    for rep in range(2):
+        out.fill_(float("nan"))
+        plan.execute()
+        torch.cuda.synchronize()
+    info = plan.info()
+    plan.destroy()
+    got = out.cpu().numpy()
+    assert info["n_wave_items"] == 0 and info["n_lane_items"] == len(medoids) * ((ds.N + 63) // 64)
+    full = run(ds)
+    self_pair = pairs[:, 0] == pairs[:, 1]
+    assert np.all(got[self_pair] == 0.0)
+    k = condensed(np.minimum(pairs[:, 0], pairs[:, 1])[~self_pair], np.maximum(pairs[:, 0], pairs[:, 1])[~self_pair],
+                  ds.N)
+    assert np.array_equal(got[~self_pair], full[k])
+    sel = np.random.default_rng(2).choice(len(pairs), 200, replace=False)
+    assert_close(got[sel], oracle_pairs(ds, pairs[sel, 0], pairs[sel, 1]), what="medoid pairs")
+
+
 # ---------------------------------------------------------------- batched plans, graph capture
 
 def _plan_for(dsets, **kw):
