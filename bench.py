@@ -50,7 +50,16 @@ WORKLOADS = {
     "c3": "long series: 500 x 4096, no window",
     "c1": "smallest: 20 x 64, no window",
     "c4": "batched uneven: 64 datasets, N in 10..400, lengths in 64..2048, mixed windows, one plan",
+    "c2m": "k-medoids assignment step on the 1000 x 512, window 51 data: every series against 10 medoids "
+           "(10,000 listed pairs, dtw_plan_create_pairs)",
 }
+MEDOIDS = 10
+
+
+def medoid_pairs(N, k, seed=230704906):
+    """Every series against k seeded medoids, as listed (series, medoid) pairs."""
+    med = np.sort(np.random.default_rng(seed).choice(N, size=k, replace=False))
+    return np.array([[i, m] for m in med for i in range(N)], dtype=np.int32)
 
 
 def make_datasets(name, dtype="f32"):
@@ -59,7 +68,8 @@ def make_datasets(name, dtype="f32"):
         return synth.config4()
     if name == "c3":
         return [synth.config3(dtype=dtype)]
-    return [{"c1": synth.config1, "c2": synth.config2, "c3": synth.config3, "c5": synth.config5}[name]()]
+    return [{"c1": synth.config1, "c2": synth.config2, "c2m": synth.config2, "c3": synth.config3,
+             "c5": synth.config5}[name]()]
 
 
 def sources_sha256(paths):
@@ -93,13 +103,15 @@ def recorded_traffic(kernel_label):
     return None
 
 
-def cpu_baseline(dsets, gpu_outs, target_s):
+def cpu_baseline(dsets, gpu_outs, target_s, pair_list=None):
     """Time the FP64 oracle on a seeded sample of pairs (all host cores) and check the GPU on them.
 
     The sample draws pairs uniformly over all datasets' pairs, puts every
     dataset's series in one buffer and times one threaded oracle call over
     them.  A pilot sample, grown until it takes half a second, sets the size
-    of the timed sample to about target_s seconds of oracle work.
+    of the timed sample to about target_s seconds of oracle work.  With
+    pair_list (one dataset), the sample is drawn from the listed pairs and
+    gpu_outs[0] is indexed like the list.
     """
     import oracle
     from paper_2307_04904_amd import synth
@@ -107,6 +119,9 @@ def cpu_baseline(dsets, gpu_outs, target_s):
     npairs = np.array([d.n_pairs for d in dsets], dtype=np.int64)
 
     def sample(k):
+        if pair_list is not None:
+            idx = rng.integers(0, len(pair_list), size=k)
+            return [(0, pair_list[idx, 0].astype(np.int32), pair_list[idx, 1].astype(np.int32), idx)]
         which = rng.choice(len(dsets), size=k, p=npairs / npairs.sum())
         out = []
         for d, ds in enumerate(dsets):
@@ -116,7 +131,10 @@ def cpu_baseline(dsets, gpu_outs, target_s):
             i = rng.integers(0, ds.N, size=3 * c + 8)
             j = rng.integers(0, ds.N, size=3 * c + 8)
             keep = i != j
-            out.append((d, np.minimum(i, j)[keep][:c].astype(np.int32), np.maximum(i, j)[keep][:c].astype(np.int32)))
+            a = np.minimum(i, j)[keep][:c].astype(np.int32)
+            b = np.maximum(i, j)[keep][:c].astype(np.int32)
+            N = ds.N
+            out.append((d, a, b, a.astype(np.int64) * N - a.astype(np.int64) * (a + 1) // 2 + (b - a - 1)))
         return out
 
     # every dataset's series in one buffer, so one oracle call spans all sampled pairs
@@ -127,15 +145,15 @@ def cpu_baseline(dsets, gpu_outs, target_s):
     lens = np.concatenate([ds.lengths for ds in dsets])
 
     def run(smp):
-        pi = np.concatenate([sbase[d] + a for d, a, _ in smp]).astype(np.int32)
-        pj = np.concatenate([sbase[d] + b for d, _, b in smp]).astype(np.int32)
-        win = np.concatenate([np.full(len(a), dsets[d].window, dtype=np.int32) for d, a, _ in smp])
+        pi = np.concatenate([sbase[d] + a for d, a, _, _ in smp]).astype(np.int32)
+        pj = np.concatenate([sbase[d] + b for d, _, b, _ in smp]).astype(np.int32)
+        win = np.concatenate([np.full(len(a), dsets[d].window, dtype=np.int32) for d, a, _, _ in smp])
         t0 = time.perf_counter()
         ref, threads = oracle.dtw_pairs(vals, offs, lens, pi, pj, win)
         t = time.perf_counter() - t0
         cells = sum(oracle.band_cells(int(lens[a]), int(lens[b]), int(w_)) for a, b, w_ in zip(pi, pj, win))
         refs, k = [], 0
-        for d, a, _ in smp:
+        for d, a, _, _ in smp:
             refs.append(ref[k:k + len(a)])
             k += len(a)
         return t, refs, cells, threads
@@ -150,9 +168,7 @@ def cpu_baseline(dsets, gpu_outs, target_s):
     smp = sample(k)
     t, refs, c, threads = run(smp)
     rels, zero_bad, n = [], 0, 0
-    for (d, pi, pj), ref in zip(smp, refs):
-        N = dsets[d].N
-        kk = pi.astype(np.int64) * N - pi.astype(np.int64) * (pi + 1) // 2 + (pj - pi - 1)
+    for (d, pi, pj, kk), ref in zip(smp, refs):
         g = gpu_outs[d][kk].astype(np.float64)
         nz = ref > 0
         rels.append(np.abs(g[nz] - ref[nz]) / ref[nz])
@@ -161,7 +177,8 @@ def cpu_baseline(dsets, gpu_outs, target_s):
     rel = np.concatenate(rels) if rels else np.zeros(0)
     return {
         "value": c / t / 1e9, "unit": "GCUPS", "cores": int(threads), "kind": "oracle",
-        "sample": "%d seeded random pairs of the same workload (%.3g admissible cells), FP64, %.1f s" % (n, c, t),
+        "sample": "%d seeded random pairs of %s (%.3g admissible cells), FP64, %.1f s" % (
+            n, "the listed pairs" if pair_list is not None else "the same workload", c, t),
     }, {"pairs_checked": n, "max_rel_err": float(rel.max()) if rel.size else 0.0,
         "mean_rel_err": float(rel.mean()) if rel.size else 0.0, "zero_mismatch": zero_bad}
 
@@ -208,11 +225,18 @@ def main(argv=None):
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     series = [binding.device_series(ds, dev) for ds in dsets]
-    outs = [torch.full((max(1, ds.n_pairs),), float("nan"), dtype=torch.float32, device=dev) for ds in dsets]
+    pair_list = medoid_pairs(dsets[0].N, MEDOIDS) if args.workload.endswith("m") else None
+    n_out = [len(pair_list)] if pair_list is not None else [ds.n_pairs for ds in dsets]
+    outs = [torch.full((max(1, k),), float("nan"), dtype=torch.float32, device=dev) for k in n_out]
     t_plan = time.perf_counter()
-    plan = binding.Plan([(s_, ds.lengths, ds.offsets, ds.window, o) for s_, ds, o in zip(series, dsets, outs)],
-                        dtype=dsets[0].dtype, accum=args.accum, kernel=args.kernel, timing=True,
-                        queue=args.dispatch == "queue", autotune=args.autotune)
+    if pair_list is not None:
+        plan = binding.PairPlan(series[0], dsets[0].lengths, dsets[0].offsets, dsets[0].window, pair_list, outs[0],
+                                dtype=dsets[0].dtype, accum=args.accum, kernel=args.kernel, timing=True,
+                                queue=args.dispatch == "queue", autotune=args.autotune)
+    else:
+        plan = binding.Plan([(s_, ds.lengths, ds.offsets, ds.window, o) for s_, ds, o in zip(series, dsets, outs)],
+                            dtype=dsets[0].dtype, accum=args.accum, kernel=args.kernel, timing=True,
+                            queue=args.dispatch == "queue", autotune=args.autotune)
     plan_s = time.perf_counter() - t_plan
     info = plan.info()
     stream = torch.cuda.current_stream(dev)
@@ -255,7 +279,8 @@ def main(argv=None):
         "vs_baseline": None,
         "dtype": "f64" if args.accum == "fp64" else "f32",
         "data": "synthetic",
-        "config": {"workload": dsets[0].name if len(dsets) == 1 else args.workload + "_batched_64_datasets",
+        "config": {"workload": (dsets[0].name + ("_medoids%d" % MEDOIDS if pair_list is not None else "")
+                                if len(dsets) == 1 else args.workload + "_batched_64_datasets"),
                    "description": WORKLOADS[args.workload], "datasets": len(dsets),
                    "N": [ds.N for ds in dsets] if len(dsets) > 1 else dsets[0].N,
                    "length": int(max(ds.lengths.max() for ds in dsets)),
@@ -281,7 +306,7 @@ def main(argv=None):
     }
     if not args.no_cpu_baseline:
         torch.cuda.synchronize(dev)
-        base, check = cpu_baseline(dsets, [o.cpu().numpy() for o in outs], args.cpu_seconds)
+        base, check = cpu_baseline(dsets, [o.cpu().numpy() for o in outs], args.cpu_seconds, pair_list)
         line["cpu_baseline"] = base
         line["gpu_vs_oracle_on_sample"] = check
     plan.destroy()
