@@ -191,6 +191,8 @@ def main(argv=None):
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--kernel", default="auto", choices=["auto", "lane", "wave", "cyclic"])
     ap.add_argument("--accum", default="plain", choices=["plain", "kahan", "fp64"])
+    ap.add_argument("--rows-per-lane", type=int, default=0,
+                    help="force the strip / cyclic rows per lane (0 = cost model)")
     ap.add_argument("--autotune", action="store_true",
                     help="plan with DTW_FLAG_AUTOTUNE (kernel instances measured per length/window bucket)")
     ap.add_argument("--dispatch", default="queue", choices=["queue", "hw"],
@@ -236,9 +238,11 @@ def main(argv=None):
     else:
         plan = binding.Plan([(s_, ds.lengths, ds.offsets, ds.window, o) for s_, ds, o in zip(series, dsets, outs)],
                             dtype=dsets[0].dtype, accum=args.accum, kernel=args.kernel, timing=True,
-                            queue=args.dispatch == "queue", autotune=args.autotune)
+                            queue=args.dispatch == "queue", autotune=args.autotune,
+                            rows_per_lane=args.rows_per_lane)
     plan_s = time.perf_counter() - t_plan
     info = plan.info()
+    plan_desc = plan.describe()
     stream = torch.cuda.current_stream(dev)
 
     for _ in range(args.warmup):
@@ -287,7 +291,9 @@ def main(argv=None):
                    "window": [ds.window for ds in dsets] if len(dsets) > 1 else dsets[0].window,
                    "pairs": info["pairs"], "band_cells": cells, "swept_cells": info["computed_cells"],
                    "kernel": args.kernel, "accum": args.accum, "storage": dsets[0].dtype,
-                   "dispatch": args.dispatch, "autotune": args.autotune,
+                   "dispatch": args.dispatch, "autotune": args.autotune, "rows_per_lane": args.rows_per_lane,
+                   "kernels": [g["kernel"] for g in plan_desc["wave_groups"]] + ["lane:%d" % g["W"] for g in
+                                                                               plan_desc["lane_groups"]],
                    "plan_create_s": round(plan_s, 3), "tuned_buckets": info["n_tuned_buckets"],
                    "tuned_changed": info["n_tuned_changed"]},
         "pct_peak_cell_rate": round(100.0 * value / (PEAK_LANE_OPS_T * 1e3 / OPS_PER_CELL), 2),

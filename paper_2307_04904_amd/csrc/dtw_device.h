@@ -107,12 +107,15 @@ struct RowCounter {  // t = s + off written as q(H+1) + h with 0 <= h <= H (q < 
         h = off - q * (H + 1);
     }
     template <int H>
-    __device__ __forceinline__ void advance() {
-        if (++h == H + 1) {
-            h = 0;
-            ++q;
-        }
+    __device__ __forceinline__ void advance() {  // two selects on one compare
+        const bool wrap = h == H;
+        const int h1 = h + 1, q1 = q + 1;
+        h = wrap ? 0 : h1;
+        q = wrap ? q1 : q;
     }
+    // Lane of the event at this slot, or -1 (no lane) for the empty slot h == H.
+    template <int H>
+    __device__ __forceinline__ int lane() const { return h < H ? q : -1; }
 };
 
 }  // namespace

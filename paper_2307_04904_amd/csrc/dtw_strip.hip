@@ -104,26 +104,23 @@ struct BandEvents {
     }
 
     // Apply the events of step s (counters are at step s on entry), then advance.
-    // Only the slot h == H (no row) needs a test.  An event whose lane q is
-    // outside 0..63 matches no lane; entries at columns <= 0 repeat the
+    // Only the slot h == H (no row) needs a test, folded into the lane
+    // compare (it names lane -1).  An event whose lane q is outside 0..63
+    // matches no lane; entries at columns <= 0 repeat the
     // start-up value; events of rows past n touch cells that never feed row
     // n-1.  Each move is a one-lane branch; the empty asm statement keeps the
     // compiler from turning it into a select of the whole register vector.
     template <int H>
     __device__ __forceinline__ void step(int s, typename XVec<H>::T &xe, const typename XVec<H>::T &xr, int lane) {
         (void)s;
-        if (en.h < H) {
-            if (lane == en.q) {
-                asm volatile("");
-                xe[en.h] = xr[en.h];
-            }
+        if (lane == en.lane<H>()) {
+            asm volatile("");
+            xe[en.h] = xr[en.h];
         }
         en.advance<H>();
-        if (ex.h < H) {
-            if (lane == ex.q) {
-                asm volatile("");
-                xe[ex.h] = kBig;
-            }
+        if (lane == ex.lane<H>()) {
+            asm volatile("");
+            xe[ex.h] = kBig;
         }
         ex.advance<H>();
     }
