@@ -194,6 +194,39 @@ int dtw_plan_create_pairs(dtw_plan *plan, const dtw_dataset *ds, const dtw_pair 
 /* Blocking form of a pair-list plan: create, execute on opt->stream, synchronise, destroy. */
 int dtw_pairs(const dtw_dataset *ds, const dtw_pair *pairs, int64_t n_pairs, float *out, const dtw_options *opt);
 
+/*
+ * Clustering scores from a condensed distance matrix D (device, N(N-1)/2
+ * floats in the order above, e.g. the output of a plan).  The paper's method,
+ * after D, clusters the series around centroid series and reports the
+ * clustering cost -- the sum of the distances between every series and its
+ * cluster's centroid -- and a silhouette score to choose the number of
+ * clusters (Introduction, list of the method's steps).  The silhouette is
+ * Rousseeuw's: a(i) = mean distance to the other members of i's cluster,
+ * b(i) = smallest mean distance to another non-empty cluster,
+ * s(i) = (b-a)/max(a,b) (0 when both are 0), 0 for a one-member cluster.
+ * All sums are FP64 in a fixed order (the same result on every run).
+ * labels (device int32[N], values 0..K-1) and centroids (device int32[K],
+ * series indices) are copied to the host and range-checked first
+ * (DTW_ERR_INVALID_ARG).  These calls allocate a device workspace, run on
+ * `stream` (hipStream_t, NULL = default) and synchronise it before
+ * returning; host outputs are valid on return.
+ */
+
+/* s (device float[N], may be NULL): s(i); *mean (host): the mean of s.
+ * 2 <= K <= 64; at least two clusters must be non-empty. */
+int dtw_silhouette(const float *D, int32_t N, const int32_t *labels, int32_t K, float *s, double *mean,
+                   void *stream);
+
+/* Clustering cost of a labelling: *total (host) = sum of D(i, centroids[labels[i]]);
+ * per_cluster (host double[K], may be NULL): the same sum per cluster.  1 <= K <= N. */
+int dtw_cluster_cost(const float *D, int32_t N, const int32_t *labels, const int32_t *centroids, int32_t K,
+                     double *per_cluster, double *total, void *stream);
+
+/* k-medoids assignment step: labels_out (device int32[N]) = index of the nearest
+ * centroid (lowest index on ties); *total and per_cluster as for dtw_cluster_cost. */
+int dtw_assign(const float *D, int32_t N, const int32_t *centroids, int32_t K, int32_t *labels_out,
+               double *per_cluster, double *total, void *stream);
+
 /* Admissible cells of one n x m problem under window w (host arithmetic only). */
 int dtw_band_cells(int32_t n, int32_t m, int32_t window, int64_t *cells);
 

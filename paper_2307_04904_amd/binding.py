@@ -24,7 +24,7 @@ DTW_FLAG_AUTOTUNE = 4
 
 EXPORTED = ["dtw_pairwise", "dtw_pairwise_ex", "dtw_plan_create", "dtw_plan_execute",
             "dtw_plan_last_kernel_ms", "dtw_plan_info", "dtw_plan_describe", "dtw_plan_destroy", "dtw_band_cells",
-            "dtw_plan_create_pairs", "dtw_pairs",
+            "dtw_plan_create_pairs", "dtw_pairs", "dtw_silhouette", "dtw_cluster_cost", "dtw_assign",
             "dtw_last_error", "dtw_version"]
 
 
@@ -251,6 +251,38 @@ class PairPlan(Plan):
         self._h = ctypes.c_void_p()
         _check(self._lib.dtw_plan_create_pairs(ctypes.byref(self._h), ctypes.byref(d), ptr, ctypes.c_int64(len(arr)),
                                                ctypes.c_void_p(out.data_ptr()), ctypes.byref(o)))
+
+
+def _dptr(t):
+    return ctypes.c_void_p(t.data_ptr() if t is not None else 0)
+
+
+def silhouette(D, N, labels, K, s_out=None, stream=None):
+    """dtw_silhouette: mean silhouette (float) of device int32 labels over the condensed device matrix D."""
+    mean = ctypes.c_double()
+    _check(load().dtw_silhouette(_dptr(D), int(N), _dptr(labels), int(K), _dptr(s_out), ctypes.byref(mean),
+                                 _stream_handle(stream)))
+    return float(mean.value)
+
+
+def cluster_cost(D, N, labels, centroids, stream=None):
+    """dtw_cluster_cost: (total, per-cluster list) of a labelling with the given centroid series."""
+    K = int(centroids.numel())
+    per = (ctypes.c_double * K)()
+    tot = ctypes.c_double()
+    _check(load().dtw_cluster_cost(_dptr(D), int(N), _dptr(labels), _dptr(centroids), K, per, ctypes.byref(tot),
+                                   _stream_handle(stream)))
+    return float(tot.value), [float(v) for v in per]
+
+
+def assign(D, N, centroids, labels_out, stream=None):
+    """dtw_assign: nearest-centroid labels into labels_out (device int32); returns (total, per-cluster list)."""
+    K = int(centroids.numel())
+    per = (ctypes.c_double * K)()
+    tot = ctypes.c_double()
+    _check(load().dtw_assign(_dptr(D), int(N), _dptr(centroids), K, _dptr(labels_out), per, ctypes.byref(tot),
+                             _stream_handle(stream)))
+    return float(tot.value), [float(v) for v in per]
 
 
 def device_series(ds, device="cuda"):

@@ -47,6 +47,19 @@ int fail(int code, const char *fmt, ...) {
     return code;
 }
 
+}  // namespace
+
+// Error reporting shared with the other host sources of the library.
+namespace dtwmi {
+int set_error(int code, const char *msg) {
+    g_err = msg;
+    return code;
+}
+void clear_error() { g_err.clear(); }
+}  // namespace dtwmi
+
+namespace {
+
 int hip_fail(hipError_t e, const char *what) {
     return fail(DTW_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
 }

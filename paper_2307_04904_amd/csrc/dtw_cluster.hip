@@ -1,0 +1,301 @@
+// Clustering scores from the condensed DTW matrix D (the method's steps after
+// D, paper Introduction: the clustering cost -- sum of the distances between
+// every series and its cluster's centroid -- and the silhouette score used to
+// choose the number of clusters; the k-medoids assignment of each series to
+// its nearest centroid).  The silhouette follows Rousseeuw's definition:
+// a(i) = mean distance to the other members of i's cluster, b(i) = smallest
+// mean distance to another non-empty cluster, s(i) = (b-a)/max(a,b) (0 when
+// both are 0), 0 for a singleton; the score is the mean of s(i).
+//
+// These kernels read D, N(N-1)/2 floats; the row-sum kernel is bound by HBM
+// bandwidth.  All sums are FP64 and every reduction has a fixed order, so
+// results do not change from run to run.
+#include "dtw_device.h"
+#include "dtwmi.h"
+
+#include <algorithm>
+#include <cstdio>
+#include <vector>
+
+namespace dtwmi {
+namespace {
+
+constexpr int kRowBlock = 64;   // rows of D per workgroup (one wavefront)
+constexpr int kReduce = 256;    // threads of the reduction kernels
+
+__device__ __forceinline__ float dist(const float *__restrict__ D, int i, int j, int N) {
+    return i == j ? 0.0f : D[i < j ? condensed_index(i, j, N) : condensed_index(j, i, N)];
+}
+
+// P[split][i][J] = sum of D(i, j) over the columns j of this split's column
+// tiles with j != i and labels[j] == J.  Workgroup (row block, split); thread t
+// owns row i0 + t and its K accumulators acc[J][t] in LDS (J uniform across
+// the wavefront, so the accesses are conflict-free).  A column tile left of
+// the diagonal reads D(j, i0..i0+63): 64 consecutive entries of row j of the
+// condensed triangle, one coalesced load per column.  A tile right of the
+// diagonal is row i's consecutive entries; it is read one condensed row at a
+// time (coalesced) into an LDS tile and consumed transposed.
+__global__ __launch_bounds__(kRowBlock) void k_row_cluster_sums(const float *__restrict__ D, int N,
+                                                                const int *__restrict__ labels, int K,
+                                                                int tiles_per_split, double *__restrict__ P) {
+    extern __shared__ double acc[];  // [K][64]
+    __shared__ float tile[kRowBlock][kRowBlock + 1];
+    const int t = threadIdx.x;
+    const int i0 = blockIdx.x * kRowBlock, i = i0 + t;
+    const int split = blockIdx.y;
+    const int n_tiles = (N + kRowBlock - 1) / kRowBlock;
+    const int jt0 = split * tiles_per_split, jt1 = min(n_tiles, jt0 + tiles_per_split);
+    for (int J = 0; J < K; ++J) acc[J * kRowBlock + t] = 0.0;
+    for (int jt = jt0; jt < jt1; ++jt) {
+        const int j0 = jt * kRowBlock;
+        const int cmax = min(kRowBlock, N - j0);
+        if (j0 + kRowBlock <= i0) {  // left of the diagonal: j < i for every j of the tile
+            if (i < N)
+                for (int c = 0; c < kRowBlock; ++c)
+                    acc[labels[j0 + c] * kRowBlock + t] += (double)D[condensed_index(j0 + c, i, N)];
+        } else if (j0 >= i0 + kRowBlock) {  // right of the diagonal: j > i
+            __syncthreads();  // the previous tile has been read
+            for (int r = 0; r < kRowBlock; ++r) {
+                const int ir = i0 + r, j = j0 + t;
+                tile[r][t] = (ir < N && j < N) ? D[condensed_index(ir, j, N)] : 0.0f;
+            }
+            __syncthreads();
+            if (i < N)
+                for (int c = 0; c < cmax; ++c) acc[labels[j0 + c] * kRowBlock + t] += (double)tile[t][c];
+        } else if (i < N) {  // the diagonal tile
+            for (int c = 0; c < cmax; ++c) {
+                const int j = j0 + c;
+                if (j != i) acc[labels[j] * kRowBlock + t] += (double)dist(D, i, j, N);
+            }
+        }
+    }
+    if (i < N)
+        for (int J = 0; J < K; ++J) P[((int64_t)split * N + i) * K + J] = acc[J * kRowBlock + t];
+}
+
+// Fixed-order tree sum of one workgroup's values into out.
+__device__ __forceinline__ void block_sum(double v, double *red, double *out) {
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = kReduce / 2; w > 0; w /= 2) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = red[0];
+}
+
+// s(i) from the cluster sums; per-workgroup partial sums of s.
+__global__ __launch_bounds__(kReduce) void k_silhouette_rows(const double *__restrict__ P, int splits, int N, int K,
+                                                             const int *__restrict__ labels,
+                                                             const int *__restrict__ sizes, float *__restrict__ s_out,
+                                                             double *__restrict__ partial) {
+    __shared__ double red[kReduce];
+    const int i = blockIdx.x * kReduce + threadIdx.x;
+    double s = 0.0;
+    if (i < N) {
+        const int A = labels[i];
+        if (sizes[A] > 1) {
+            double a = 0.0, b = __builtin_huge_val();
+            for (int J = 0; J < K; ++J) {
+                double sum = 0.0;
+                for (int sp = 0; sp < splits; ++sp) sum += P[((int64_t)sp * N + i) * K + J];
+                if (J == A)
+                    a = sum / (double)(sizes[A] - 1);
+                else if (sizes[J] > 0)
+                    b = fmin(b, sum / (double)sizes[J]);
+            }
+            const double m = fmax(a, b);
+            s = m == 0.0 ? 0.0 : (b - a) / m;
+        }
+        if (s_out) s_out[i] = (float)s;
+    }
+    block_sum(s, red, partial + blockIdx.x);
+}
+
+// Distance of each series to its own centroid (cost) or to its nearest
+// centroid (assignment, lowest cluster index on ties).
+__global__ __launch_bounds__(kReduce) void k_centroid_dist(const float *__restrict__ D, int N,
+                                                           const int *__restrict__ labels,
+                                                           const int *__restrict__ centroids, int K,
+                                                           int *__restrict__ labels_out, double *__restrict__ v) {
+    const int i = blockIdx.x * kReduce + threadIdx.x;
+    if (i >= N) return;
+    if (labels) {
+        v[i] = (double)dist(D, i, centroids[labels[i]], N);
+        return;
+    }
+    float best = __builtin_huge_valf();
+    int lab = 0;
+    for (int c = 0; c < K; ++c) {
+        const float d = dist(D, i, centroids[c], N);
+        if (d < best) {
+            best = d;
+            lab = c;
+        }
+    }
+    labels_out[i] = lab;
+    v[i] = (double)best;
+}
+
+// One workgroup: out[J] = sum of v[i] over the series with key[i] == J (key ==
+// nullptr: all series into out[0]), each thread over i = t, t+256, ... then a
+// tree, J after J.
+__global__ __launch_bounds__(kReduce) void k_sum_by_key(const double *__restrict__ v, int n,
+                                                        const int *__restrict__ key, int K, double *__restrict__ out) {
+    __shared__ double red[kReduce];
+    for (int J = 0; J < K; ++J) {
+        double s = 0.0;
+        for (int i = threadIdx.x; i < n; i += kReduce)
+            if (!key || key[i] == J) s += v[i];
+        block_sum(s, red, out + J);
+        __syncthreads();
+    }
+}
+
+// ---- host side ----
+int fail_msg(int code, const char *fmt, long long a = 0, long long b = 0, long long c = 0) {
+    char buf[256];
+    snprintf(buf, sizeof buf, fmt, a, b, c);
+    return set_error(code, buf);
+}
+
+int hip_err(hipError_t e, const char *what) {
+    char buf[256];
+    snprintf(buf, sizeof buf, "%s: %s", what, hipGetErrorString(e));
+    return set_error(DTW_ERR_HIP, buf);
+}
+
+// Device labels or centroids copied to the host and range-checked.
+int fetch_indices(const int32_t *dev, int64_t n, int32_t limit, const char *what, std::vector<int32_t> &host,
+                  hipStream_t s) {
+    host.resize((size_t)n);
+    hipError_t e = hipMemcpyAsync(host.data(), dev, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_err(e, "hipMemcpy (indices)");
+    for (int64_t k = 0; k < n; ++k)
+        if (host[(size_t)k] < 0 || host[(size_t)k] >= limit) {
+            char buf[160];
+            snprintf(buf, sizeof buf, "%s[%lld] = %d outside 0..%d", what, (long long)k, host[(size_t)k], limit - 1);
+            return set_error(DTW_ERR_INVALID_ARG, buf);
+        }
+    return DTW_OK;
+}
+
+// Owns the device workspace of one call.
+struct Scratch {
+    void *p = nullptr;
+    ~Scratch() {
+        if (p) (void)hipFree(p);
+    }
+};
+
+}  // namespace
+}  // namespace dtwmi
+
+using namespace dtwmi;
+
+extern "C" {
+
+int dtw_silhouette(const float *D, int32_t N, const int32_t *labels, int32_t K, float *s_out, double *mean,
+                   void *stream) {
+    clear_error();
+    if (!D || !labels || !mean) return set_error(DTW_ERR_INVALID_ARG, "D, labels or mean is NULL");
+    if (N < 2) return fail_msg(DTW_ERR_INVALID_ARG, "N=%lld < 2", N);
+    if (K < 2 || K > kSilhouetteMaxK)
+        return fail_msg(K < 2 ? DTW_ERR_INVALID_ARG : DTW_ERR_UNSUPPORTED, "K=%lld outside 2..%lld", K,
+                        kSilhouetteMaxK);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    std::vector<int32_t> lab;
+    int rc = fetch_indices(labels, N, K, "labels", lab, s);
+    if (rc) return rc;
+    std::vector<int32_t> sizes(K, 0);
+    for (int32_t l : lab) ++sizes[l];
+    if (std::count_if(sizes.begin(), sizes.end(), [](int32_t z) { return z > 0; }) < 2)
+        return set_error(DTW_ERR_INVALID_ARG, "the silhouette needs at least two non-empty clusters");
+
+    const int row_blocks = (N + kRowBlock - 1) / kRowBlock;
+    const int n_tiles = row_blocks;
+    const int splits = std::max(1, std::min(n_tiles, (2048 + row_blocks - 1) / row_blocks));
+    const int tiles_per_split = (n_tiles + splits - 1) / splits;
+    const int red_blocks = (N + kReduce - 1) / kReduce;
+    const size_t o_sizes = 0, o_P = 256, bytes_P = (size_t)splits * N * K * sizeof(double);
+    const size_t o_part = o_P + ((bytes_P + 255) / 256) * 256;
+    const size_t o_out = o_part + ((red_blocks * sizeof(double) + 255) / 256) * 256;
+    Scratch w;
+    hipError_t e = hipMalloc(&w.p, o_out + 256);
+    if (e != hipSuccess) return set_error(DTW_ERR_OUT_OF_MEMORY, "workspace allocation failed");
+    char *base = static_cast<char *>(w.p);
+    int *d_sizes = reinterpret_cast<int *>(base + o_sizes);
+    double *d_P = reinterpret_cast<double *>(base + o_P);
+    double *d_part = reinterpret_cast<double *>(base + o_part);
+    double *d_out = reinterpret_cast<double *>(base + o_out);
+    e = hipMemcpyAsync(d_sizes, sizes.data(), K * sizeof(int32_t), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_err(e, "hipMemcpy (cluster sizes)");
+    hipLaunchKernelGGL(k_row_cluster_sums, dim3(row_blocks, splits), dim3(kRowBlock),
+                       (size_t)K * kRowBlock * sizeof(double), s, D, N, labels, K, tiles_per_split, d_P);
+    if ((e = hipGetLastError()) != hipSuccess) return hip_err(e, "row-sum kernel launch");
+    hipLaunchKernelGGL(k_silhouette_rows, dim3(red_blocks), dim3(kReduce), 0, s, d_P, splits, N, K, labels, d_sizes,
+                       s_out, d_part);
+    if ((e = hipGetLastError()) != hipSuccess) return hip_err(e, "silhouette kernel launch");
+    hipLaunchKernelGGL(k_sum_by_key, dim3(1), dim3(kReduce), 0, s, d_part, red_blocks, nullptr, 1, d_out);
+    if ((e = hipGetLastError()) != hipSuccess) return hip_err(e, "reduction kernel launch");
+    double total = 0.0;
+    e = hipMemcpyAsync(&total, d_out, sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_err(e, "silhouette result");
+    *mean = total / (double)N;
+    return DTW_OK;
+}
+
+// Shared body of the cost and assignment entry points.
+static int centroid_scores(const float *D, int32_t N, const int32_t *labels, const int32_t *centroids, int32_t K,
+                           int32_t *labels_out, double *per_cluster, double *total, void *stream) {
+    clear_error();
+    if (!D || !centroids || !total) return set_error(DTW_ERR_INVALID_ARG, "D, centroids or total is NULL");
+    if (!labels && !labels_out) return set_error(DTW_ERR_INVALID_ARG, "labels_out is NULL");
+    if (N < 2) return fail_msg(DTW_ERR_INVALID_ARG, "N=%lld < 2", N);
+    if (K < 1 || K > N) return fail_msg(DTW_ERR_INVALID_ARG, "K=%lld outside 1..%lld", K, N);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    std::vector<int32_t> host;
+    int rc = fetch_indices(centroids, K, N, "centroids", host, s);
+    if (!rc && labels) rc = fetch_indices(labels, N, K, "labels", host, s);
+    if (rc) return rc;
+    const int blocks = (N + kReduce - 1) / kReduce;
+    const size_t o_v = 0, o_out = (((size_t)N * sizeof(double) + 255) / 256) * 256;
+    Scratch w;
+    hipError_t e = hipMalloc(&w.p, o_out + (size_t)(K + 1) * sizeof(double));
+    if (e != hipSuccess) return set_error(DTW_ERR_OUT_OF_MEMORY, "workspace allocation failed");
+    double *d_v = reinterpret_cast<double *>(static_cast<char *>(w.p) + o_v);
+    double *d_out = reinterpret_cast<double *>(static_cast<char *>(w.p) + o_out);
+    hipLaunchKernelGGL(k_centroid_dist, dim3(blocks), dim3(kReduce), 0, s, D, N, labels, centroids, K, labels_out, d_v);
+    if ((e = hipGetLastError()) != hipSuccess) return hip_err(e, "centroid kernel launch");
+    hipLaunchKernelGGL(k_sum_by_key, dim3(1), dim3(kReduce), 0, s, d_v, N, nullptr, 1, d_out + K);
+    if ((e = hipGetLastError()) != hipSuccess) return hip_err(e, "reduction kernel launch");
+    if (per_cluster) {
+        hipLaunchKernelGGL(k_sum_by_key, dim3(1), dim3(kReduce), 0, s, d_v, N, labels ? labels : labels_out, K, d_out);
+        if ((e = hipGetLastError()) != hipSuccess) return hip_err(e, "reduction kernel launch");
+    }
+    std::vector<double> res(K + 1);
+    e = hipMemcpyAsync(res.data(), d_out, (K + 1) * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_err(e, "cluster cost result");
+    *total = res[K];
+    if (per_cluster) std::copy(res.begin(), res.begin() + K, per_cluster);
+    return DTW_OK;
+}
+
+int dtw_cluster_cost(const float *D, int32_t N, const int32_t *labels, const int32_t *centroids, int32_t K,
+                     double *per_cluster, double *total, void *stream) {
+    if (!labels) {
+        clear_error();
+        return set_error(DTW_ERR_INVALID_ARG, "labels is NULL");
+    }
+    return centroid_scores(D, N, labels, centroids, K, nullptr, per_cluster, total, stream);
+}
+
+int dtw_assign(const float *D, int32_t N, const int32_t *centroids, int32_t K, int32_t *labels_out,
+               double *per_cluster, double *total, void *stream) {
+    return centroid_scores(D, N, nullptr, centroids, K, labels_out, per_cluster, total, stream);
+}
+
+}  // extern "C"

@@ -95,4 +95,12 @@ int cyclic_resident(int H);
 hipError_t launch_cyclic(int H, const float *ws, const SeriesInfo *ser, const DatasetInfo *dsi,
                          const WaveItem *items, unsigned n_items, unsigned *queue, int slots, hipStream_t stream);
 
+// Last-error message of the calling thread (dtw_last_error), for every host
+// source of the library: set_error stores msg and returns code.
+int set_error(int code, const char *msg);
+void clear_error();
+
+// Clustering scores from a condensed distance matrix (dtw_cluster.hip).
+constexpr int kSilhouetteMaxK = 64;  // clusters held in LDS by the row-sum kernel
+
 }  // namespace dtwmi

@@ -117,6 +117,19 @@ def test_pair_list_validation_on_host():
     assert lib.dtw_plan_create_pairs(None, None, None, ctypes.c_int64(0), None, None) == B.DTW_ERR_INVALID_ARG
 
 
+def test_cluster_score_arguments_rejected_on_host():
+    lib = B.load()
+    mean, tot = ctypes.c_double(), ctypes.c_double()
+    dev = ctypes.c_void_p(FAKE_DEV)
+    assert lib.dtw_silhouette(None, 10, dev, 2, None, ctypes.byref(mean), None) == B.DTW_ERR_INVALID_ARG
+    assert lib.dtw_silhouette(dev, 1, dev, 2, None, ctypes.byref(mean), None) == B.DTW_ERR_INVALID_ARG
+    assert lib.dtw_silhouette(dev, 10, dev, 1, None, ctypes.byref(mean), None) == B.DTW_ERR_INVALID_ARG
+    assert lib.dtw_silhouette(dev, 10, dev, 65, None, ctypes.byref(mean), None) == B.DTW_ERR_UNSUPPORTED
+    assert lib.dtw_cluster_cost(dev, 10, None, dev, 2, None, ctypes.byref(tot), None) == B.DTW_ERR_INVALID_ARG
+    assert lib.dtw_assign(dev, 10, dev, 11, dev, None, ctypes.byref(tot), None) == B.DTW_ERR_INVALID_ARG
+    assert lib.dtw_assign(dev, 10, dev, 2, None, None, ctypes.byref(tot), None) == B.DTW_ERR_INVALID_ARG
+
+
 def test_fewer_than_two_series_is_a_no_op():
     # no HIP call is made: this passes on a machine without a GPU
     assert _call_ex([], [], series=0, out=0)[0] == B.DTW_OK
