@@ -193,6 +193,8 @@ def main(argv=None):
     ap.add_argument("--accum", default="plain", choices=["plain", "kahan", "fp64"])
     ap.add_argument("--rows-per-lane", type=int, default=0,
                     help="force the strip / cyclic rows per lane (0 = cost model)")
+    ap.add_argument("--silhouette", type=int, default=0, metavar="K",
+                    help="also time dtw_silhouette on the computed matrix with K seeded random clusters")
     ap.add_argument("--autotune", action="store_true",
                     help="plan with DTW_FLAG_AUTOTUNE (kernel instances measured per length/window bucket)")
     ap.add_argument("--dispatch", default="queue", choices=["queue", "hw"],
@@ -310,6 +312,16 @@ def main(argv=None):
         },
         "wall_s": round(wall, 3),
     }
+    if args.silhouette and len(dsets) == 1 and pair_list is None:
+        N, K = dsets[0].N, args.silhouette
+        labels = torch.from_numpy(np.random.default_rng(7).integers(0, K, size=N).astype(np.int32)).to(dev)
+        walls = []
+        for _ in range(5):
+            t0 = time.perf_counter()
+            mean = binding.silhouette(outs[0], N, labels, K, stream=stream)
+            walls.append(time.perf_counter() - t0)
+        line["silhouette"] = {"K": K, "mean": mean, "call_ms_min": round(1e3 * min(walls), 3),
+                              "matrix_bytes": 4 * N * (N - 1) // 2}
     if not args.no_cpu_baseline:
         torch.cuda.synchronize(dev)
         base, check = cpu_baseline(dsets, [o.cpu().numpy() for o in outs], args.cpu_seconds, pair_list)

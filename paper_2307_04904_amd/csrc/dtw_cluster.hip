@@ -20,7 +20,9 @@
 namespace dtwmi {
 namespace {
 
-constexpr int kRowBlock = 64;   // rows of D per workgroup (one wavefront)
+constexpr int kRowBlock = 64;   // rows of D per workgroup (one row per lane)
+constexpr int kMaxWaves = 4;    // wavefronts per row-sum workgroup, each with its own accumulators
+constexpr int kSumWaves = 1;    // wavefronts the launcher uses (measured: one per workgroup is fastest)
 constexpr int kReduce = 256;    // threads of the reduction kernels
 
 __device__ __forceinline__ float dist(const float *__restrict__ D, int i, int j, int N) {
@@ -28,49 +30,61 @@ __device__ __forceinline__ float dist(const float *__restrict__ D, int i, int j,
 }
 
 // P[split][i][J] = sum of D(i, j) over the columns j of this split's column
-// tiles with j != i and labels[j] == J.  Workgroup (row block, split); thread t
-// owns row i0 + t and its K accumulators acc[J][t] in LDS (J uniform across
-// the wavefront, so the accesses are conflict-free).  A column tile left of
-// the diagonal reads D(j, i0..i0+63): 64 consecutive entries of row j of the
-// condensed triangle, one coalesced load per column.  A tile right of the
-// diagonal is row i's consecutive entries; it is read one condensed row at a
-// time (coalesced) into an LDS tile and consumed transposed.
-__global__ __launch_bounds__(kRowBlock) void k_row_cluster_sums(const float *__restrict__ D, int N,
-                                                                const int *__restrict__ labels, int K,
-                                                                int tiles_per_split, double *__restrict__ P) {
-    extern __shared__ double acc[];  // [K][64]
-    __shared__ float tile[kRowBlock][kRowBlock + 1];
-    const int t = threadIdx.x;
+// tiles with j != i and labels[j] == J.  Workgroup (row block, split) of W
+// wavefronts; wavefront w sweeps every W-th tile of the split, and its thread
+// t owns row i0 + t and K accumulators acc[w][J][t] in LDS (J uniform across
+// the wavefront, so the accesses are conflict-free); the W partial sums are
+// added in wavefront order at the end.  A column tile left of the diagonal
+// reads D(j, i0..i0+63): 64 consecutive entries of row j of the condensed
+// triangle, one coalesced load per column.  Right of the diagonal each thread
+// reads the 64 consecutive entries D(i, j0..j0+63) of its own row: every
+// cache line a wavefront touches is used whole over the tile.  Each tile's 64
+// labels are staged in LDS and its 64 values per thread loaded into registers
+// before any accumulation, so a tile's loads are all in flight at once.
+// Entries outside the matrix or on the diagonal contribute 0.
+__global__ __launch_bounds__(kRowBlock * kMaxWaves) void k_row_cluster_sums(const float *__restrict__ D, int N,
+                                                                            const int *__restrict__ labels, int K,
+                                                                            int tiles_per_split,
+                                                                            double *__restrict__ P) {
+    extern __shared__ double acc[];  // [W][K][64]
+    __shared__ int lab[kMaxWaves][kRowBlock];
+    const int t = threadIdx.x & (kRowBlock - 1);
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kRowBlock), W = blockDim.x / kRowBlock;
+    double *my = acc + (size_t)w * K * kRowBlock;
     const int i0 = blockIdx.x * kRowBlock, i = i0 + t;
     const int split = blockIdx.y;
     const int n_tiles = (N + kRowBlock - 1) / kRowBlock;
     const int jt0 = split * tiles_per_split, jt1 = min(n_tiles, jt0 + tiles_per_split);
-    for (int J = 0; J < K; ++J) acc[J * kRowBlock + t] = 0.0;
-    for (int jt = jt0; jt < jt1; ++jt) {
+    for (int J = 0; J < K; ++J) my[J * kRowBlock + t] = 0.0;
+    for (int jt = jt0 + w; jt < jt1; jt += W) {  // tiles of this wavefront: only wave-local LDS below
         const int j0 = jt * kRowBlock;
-        const int cmax = min(kRowBlock, N - j0);
-        if (j0 + kRowBlock <= i0) {  // left of the diagonal: j < i for every j of the tile
-            if (i < N)
-                for (int c = 0; c < kRowBlock; ++c)
-                    acc[labels[j0 + c] * kRowBlock + t] += (double)D[condensed_index(j0 + c, i, N)];
-        } else if (j0 >= i0 + kRowBlock) {  // right of the diagonal: j > i
-            __syncthreads();  // the previous tile has been read
-            for (int r = 0; r < kRowBlock; ++r) {
-                const int ir = i0 + r, j = j0 + t;
-                tile[r][t] = (ir < N && j < N) ? D[condensed_index(ir, j, N)] : 0.0f;
-            }
-            __syncthreads();
-            if (i < N)
-                for (int c = 0; c < cmax; ++c) acc[labels[j0 + c] * kRowBlock + t] += (double)tile[t][c];
-        } else if (i < N) {  // the diagonal tile
-            for (int c = 0; c < cmax; ++c) {
-                const int j = j0 + c;
-                if (j != i) acc[labels[j] * kRowBlock + t] += (double)dist(D, i, j, N);
-            }
+        // lab[w] is this wavefront's own: its lanes run in lockstep and its LDS
+        // accesses complete in order, so only the compiler must keep the order
+        lab[w][t] = j0 + t < N ? labels[j0 + t] : 0;
+        __builtin_amdgcn_wave_barrier();
+        float v[kRowBlock];
+        if (j0 + kRowBlock <= i0) {  // left of the diagonal: D(j, i), consecutive in i
+#pragma unroll
+            for (int c = 0; c < kRowBlock; ++c) v[c] = i < N ? D[condensed_index(j0 + c, i, N)] : 0.0f;
+        } else if (j0 >= i0 + kRowBlock) {  // right of the diagonal: D(i, j), consecutive in j
+            const int64_t rb = i < N ? condensed_index(i, j0, N) : 0;
+#pragma unroll
+            for (int c = 0; c < kRowBlock; ++c) v[c] = (i < N && j0 + c < N) ? D[rb + c] : 0.0f;
+        } else {  // the diagonal tile
+#pragma unroll
+            for (int c = 0; c < kRowBlock; ++c) v[c] = (i < N && j0 + c < N) ? dist(D, i, j0 + c, N) : 0.0f;
         }
+#pragma unroll
+        for (int c = 0; c < kRowBlock; ++c) my[lab[w][c] * kRowBlock + t] += (double)v[c];
+        __builtin_amdgcn_wave_barrier();  // reads of lab[w] before the next tile's writes
     }
-    if (i < N)
-        for (int J = 0; J < K; ++J) P[((int64_t)split * N + i) * K + J] = acc[J * kRowBlock + t];
+    __syncthreads();  // every wavefront reaches this once
+    if (w == 0 && i < N)
+        for (int J = 0; J < K; ++J) {
+            double sum = 0.0;
+            for (int u = 0; u < W; ++u) sum += acc[((size_t)u * K + J) * kRowBlock + t];
+            P[((int64_t)split * N + i) * K + J] = sum;
+        }
 }
 
 // Fixed-order tree sum of one workgroup's values into out.
@@ -213,9 +227,14 @@ int dtw_silhouette(const float *D, int32_t N, const int32_t *labels, int32_t K, 
     if (std::count_if(sizes.begin(), sizes.end(), [](int32_t z) { return z > 0; }) < 2)
         return set_error(DTW_ERR_INVALID_ARG, "the silhouette needs at least two non-empty clusters");
 
+    // Wavefronts per workgroup: up to 4, with their accumulators within 64 KB of
+    // LDS; enough workgroups for ~8 wavefronts per SIMD, each wavefront with at
+    // least one column tile.
     const int row_blocks = (N + kRowBlock - 1) / kRowBlock;
     const int n_tiles = row_blocks;
-    const int splits = std::max(1, std::min(n_tiles, (2048 + row_blocks - 1) / row_blocks));
+    const int waves = std::max(1, std::min(kSumWaves, 65536 / (K * kRowBlock * (int)sizeof(double))));
+    const int target_groups = 2048 / waves;
+    const int splits = std::max(1, std::min((n_tiles + waves - 1) / waves, (target_groups + row_blocks - 1) / row_blocks));
     const int tiles_per_split = (n_tiles + splits - 1) / splits;
     const int red_blocks = (N + kReduce - 1) / kReduce;
     const size_t o_sizes = 0, o_P = 256, bytes_P = (size_t)splits * N * K * sizeof(double);
@@ -231,8 +250,8 @@ int dtw_silhouette(const float *D, int32_t N, const int32_t *labels, int32_t K, 
     double *d_out = reinterpret_cast<double *>(base + o_out);
     e = hipMemcpyAsync(d_sizes, sizes.data(), K * sizeof(int32_t), hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return hip_err(e, "hipMemcpy (cluster sizes)");
-    hipLaunchKernelGGL(k_row_cluster_sums, dim3(row_blocks, splits), dim3(kRowBlock),
-                       (size_t)K * kRowBlock * sizeof(double), s, D, N, labels, K, tiles_per_split, d_P);
+    hipLaunchKernelGGL(k_row_cluster_sums, dim3(row_blocks, splits), dim3(kRowBlock * waves),
+                       (size_t)waves * K * kRowBlock * sizeof(double), s, D, N, labels, K, tiles_per_split, d_P);
     if ((e = hipGetLastError()) != hipSuccess) return hip_err(e, "row-sum kernel launch");
     hipLaunchKernelGGL(k_silhouette_rows, dim3(red_blocks), dim3(kReduce), 0, s, d_P, splits, N, K, labels, d_sizes,
                        s_out, d_part);
