@@ -227,6 +227,29 @@ int dtw_cluster_cost(const float *D, int32_t N, const int32_t *labels, const int
 int dtw_assign(const float *D, int32_t N, const int32_t *centroids, int32_t K, int32_t *labels_out,
                double *per_cluster, double *total, void *stream);
 
+/*
+ * Optimal warping path of one pair (paper, "Mathematical background" and
+ * Fig. 1): the cells (i, j) matched by the cheapest alignment of x and y, from
+ * (0, 0) to (n-1, m-1) (0-based), found by walking back through the cumulative
+ * cost matrix of Eq. (c) from its last cell, each time to the predecessor with
+ * the smallest cumulative cost; ties go to the diagonal (i-1, j-1), then
+ * (i-1, j), then (i, j-1).  The window rule is the one above.  PLAIN FP32
+ * accumulation: *cost equals the distance-matrix entry of the pair.
+ *   x (device, n floats), y (device, m floats): the two series, n, m >= 1;
+ *     the shorter may have up to 32768 points (else DTW_ERR_UNSUPPORTED).
+ *   path (device int32[2*(n+m-1)]): the path as (i, j) pairs in order from
+ *     (0, 0); *path_len (host) receives its number of cells (n+m-1 at most).
+ *   *cost (host): c(n, m).
+ *   C (device float[n*m], may be NULL): the cumulative cost matrix, row-major,
+ *     C[i*m + j] = c(i+1, j+1), +inf at inadmissible cells.
+ * If c(n, m) is not finite (FP32 overflow) the path is admissible but not meaningful.
+ * Allocates a device workspace of about 4 bytes per cell of the n x m matrix
+ * (plus padding), runs on `stream` (hipStream_t, NULL = default) and
+ * synchronises it before returning.
+ */
+int dtw_path(const float *x, int32_t n, const float *y, int32_t m, int32_t window, int32_t *path,
+             int64_t *path_len, float *cost, float *C, void *stream);
+
 /* Admissible cells of one n x m problem under window w (host arithmetic only). */
 int dtw_band_cells(int32_t n, int32_t m, int32_t window, int64_t *cells);
 

@@ -25,7 +25,7 @@ DTW_FLAG_AUTOTUNE = 4
 EXPORTED = ["dtw_pairwise", "dtw_pairwise_ex", "dtw_plan_create", "dtw_plan_execute",
             "dtw_plan_last_kernel_ms", "dtw_plan_info", "dtw_plan_describe", "dtw_plan_destroy", "dtw_band_cells",
             "dtw_plan_create_pairs", "dtw_pairs", "dtw_silhouette", "dtw_cluster_cost", "dtw_assign",
-            "dtw_last_error", "dtw_version"]
+            "dtw_path", "dtw_last_error", "dtw_version"]
 
 
 class DtwError(RuntimeError):
@@ -283,6 +283,23 @@ def assign(D, N, centroids, labels_out, stream=None):
     _check(load().dtw_assign(_dptr(D), int(N), _dptr(centroids), K, _dptr(labels_out), per, ctypes.byref(tot),
                              _stream_handle(stream)))
     return float(tot.value), [float(v) for v in per]
+
+
+def warping_path(x, y, window=-1, path_out=None, C_out=None, stream=None):
+    """dtw_path: the optimal warping path of device series x, y.
+
+    Returns (path, cost): path is the leading (L, 2) int32 view of path_out (a
+    device tensor of 2*(n+m-1) int32, allocated here if None), cost the float
+    c(n, m).  C_out (device float32, n*m) receives the row-major cost matrix.
+    """
+    import torch
+    n, m = int(x.numel()), int(y.numel())
+    if path_out is None:
+        path_out = torch.empty(2 * (n + m - 1), dtype=torch.int32, device=x.device)
+    length, cost = ctypes.c_int64(), ctypes.c_float()
+    _check(load().dtw_path(_dptr(x), n, _dptr(y), m, int(window), _dptr(path_out), ctypes.byref(length),
+                           ctypes.byref(cost), _dptr(C_out), _stream_handle(stream)))
+    return path_out[: 2 * length.value].view(-1, 2), float(cost.value)
 
 
 def device_series(ds, device="cuda"):

@@ -130,6 +130,26 @@ def test_cluster_score_arguments_rejected_on_host():
     assert lib.dtw_assign(dev, 10, dev, 2, None, None, ctypes.byref(tot), None) == B.DTW_ERR_INVALID_ARG
 
 
+def test_path_arguments_rejected_on_host():
+    lib = B.load()
+    dev = ctypes.c_void_p(FAKE_DEV)
+    ln, cost = ctypes.c_int64(), ctypes.c_float()
+
+    def call(x=dev, n=4, y=dev, m=4, path=dev, length=True, c=True):
+        rc = lib.dtw_path(x, n, y, m, -1, path, ctypes.byref(ln) if length else None,
+                          ctypes.byref(cost) if c else None, None, None)
+        return rc, B.dtw_last_error()
+
+    assert call(x=None)[0] == B.DTW_ERR_INVALID_ARG
+    assert call(path=None)[0] == B.DTW_ERR_INVALID_ARG
+    assert call(length=False)[0] == B.DTW_ERR_INVALID_ARG
+    assert call(c=False)[0] == B.DTW_ERR_INVALID_ARG
+    assert call(n=0)[0] == B.DTW_ERR_INVALID_ARG
+    assert call(m=-1)[0] == B.DTW_ERR_INVALID_ARG
+    rc, msg = call(n=32769, m=40000)
+    assert rc == B.DTW_ERR_UNSUPPORTED and "32768" in msg
+
+
 def test_fewer_than_two_series_is_a_no_op():
     # no HIP call is made: this passes on a machine without a GPU
     assert _call_ex([], [], series=0, out=0)[0] == B.DTW_OK
