@@ -195,6 +195,8 @@ def main(argv=None):
                     help="force the strip / cyclic rows per lane (0 = cost model)")
     ap.add_argument("--silhouette", type=int, default=0, metavar="K",
                     help="also time dtw_silhouette on the computed matrix with K seeded random clusters")
+    ap.add_argument("--path", action="store_true",
+                    help="also time dtw_path (cost matrix, backtrack, row-major matrix) on series 0 and 1")
     ap.add_argument("--autotune", action="store_true",
                     help="plan with DTW_FLAG_AUTOTUNE (kernel instances measured per length/window bucket)")
     ap.add_argument("--dispatch", default="queue", choices=["queue", "hw"],
@@ -322,6 +324,23 @@ def main(argv=None):
             walls.append(time.perf_counter() - t0)
         line["silhouette"] = {"K": K, "mean": mean, "call_ms_min": round(1e3 * min(walls), 3),
                               "matrix_bytes": 4 * N * (N - 1) // 2}
+    if args.path and dsets[0].dtype == "f32":
+        ds = dsets[0]
+        o0, o1 = int(ds.offsets[0]), int(ds.offsets[1])
+        n, m = int(ds.lengths[0]), int(ds.lengths[1])
+        x = series[0][o0:o0 + n].float().contiguous()
+        y = series[0][o1:o1 + m].float().contiguous()
+        buf = torch.empty(2 * (n + m - 1), dtype=torch.int32, device=dev)
+        Cm = torch.empty(n * m, dtype=torch.float32, device=dev)
+        res = {}
+        for tag, C_out in (("path", None), ("path_and_matrix", Cm)):
+            walls = []
+            for _ in range(5):
+                t0 = time.perf_counter()
+                p, cost = binding.warping_path(x, y, ds.window, path_out=buf, C_out=C_out, stream=stream)
+                walls.append(time.perf_counter() - t0)
+            res[tag + "_call_ms_min"] = round(1e3 * min(walls), 3)
+        line["path"] = dict(n=n, m=m, window=ds.window, cells=n * m, path_cells=int(p.shape[0]), cost=cost, **res)
     if not args.no_cpu_baseline:
         torch.cuda.synchronize(dev)
         base, check = cpu_baseline(dsets, [o.cpu().numpy() for o in outs], args.cpu_seconds, pair_list)
