@@ -8,10 +8,10 @@
 // [(64g+l)H, (64g+l)H+H) of the shorter series, column s - l - g(64+kLag) at
 // step s, the strip's bottom cell passed down by DPP and between wavefronts
 // through an LDS ring -- and stores every cell.  The store layout follows the
-// sweep, not the matrix: at step s wavefront g writes its H rows as H
-// contiguous 64-lane runs, Z[((s*G + g)*H + h)*64 + l], so every store is one
-// coalesced 256-byte line.  k_backtrack reads that layout through zindex();
-// k_row_major rewrites it as the row-major matrix when the caller asks for it.
+// sweep, not the matrix: at step s wavefront g writes one contiguous block of
+// 64*H floats, lane l's H cells at Z[((s*G + g)*64 + l)*H + h], as 16-byte
+// vector stores.  k_backtrack reads that layout through zindex(); k_row_major
+// rewrites it as the row-major matrix when the caller asks for it.
 #include "dtw_device.h"
 #include "dtwmi.h"
 
@@ -35,7 +35,7 @@ __device__ __forceinline__ int64_t zindex(const PathGeom &g, int r, int c) {
     const int L = r >> g.logH, h = r & (g.H - 1);
     const int wave = L >> 6, lane = L & 63;
     const int64_t s = (int64_t)c + lane + wave * (64 + kLag);
-    return ((s * g.G + wave) * g.H + h) * 64 + lane;
+    return ((s * g.G + wave) * 64 + lane) * g.H + h;
 }
 
 // c(i+1, j+1) of Eq. (c) for 0-based (i, j) in the caller's orientation (i
@@ -54,28 +54,48 @@ __global__ __launch_bounds__(64 * G) void k_cost_matrix(const float *__restrict_
     const int na = geo.na, nb = geo.nb;
     const int rbase = (wave * 64 + lane) * H;
     const int skew = lane + wave * (64 + kLag);  // column = s - skew
+    const int col0 = -wave * (64 + kLag);        // column of lane 0 at step 0
 
-    float x[H], O[H];
+    float x[H], A[H], B[H];
 #pragma unroll
     for (int h = 0; h < H; ++h) {
         const int r = rbase + h;
         x[h] = r < na ? a[r] : 0.0f;  // rows past na never feed a row below na
-        O[h] = kInf;
+        A[h] = kInf;
     }
     if constexpr (G > 1) {
         for (int k = threadIdx.x; k < (G - 1) * kPRing; k += 64 * G) ring[k / kPRing][k % kPRing] = kInf;
         __syncthreads();
     }
+    // y travels down the lanes with the anti-diagonal: lane l at step s uses
+    // the y lane l-1 used at step s-1, and lane 0 takes y[s + col0] from a
+    // 64-value block loaded one block ahead (lane q holds y[s0 + q + col0]).
+    // Columns outside 0..nb-1 read the nearest end value: cells of columns
+    // before 0 see only +inf neighbours, cells past nb-1 are never read back
+    // and never feed a column below nb.
+    auto yblock = [&](int s0) {
+        const int c = s0 + lane + col0;
+        return b[c < 0 ? 0 : (c >= nb ? nb - 1 : c)];
+    };
+    float ynext = yblock(0), yv = 0.0f;
     float up_in = kInf;
     float diag_in = (lane == 0 && wave == 0) ? 0.0f : kInf;  // c(0,0) of the 1-based recurrence
-    float *__restrict__ zw = Z + (int64_t)wave * H * 64 + lane;
-    const int64_t zstep = (int64_t)G * H * 64;
+    // sweep-order store: lane-major within a step, H contiguous floats per lane
+    float *__restrict__ zl = Z + ((int64_t)wave * 64 + lane) * H;
+    const int64_t zstep = (int64_t)G * 64 * H;
 
-    for (int s = 0; s < geo.steps; ++s) {
+    // One step: column s - skew of this lane's H rows, from the previous
+    // column Oi into Oo (two steps per iteration ping-pong the arrays).
+    auto step = [&](int s, float ycur, int qs, const float (&Oi)[H], float (&Oo)[H]) {
+        // lane 0's up neighbour for step s+1: column s+1 - wave(64+kLag) of
+        // the wavefront above, written by it at the end of step s+1-kLag (a
+        // barrier lies between); read early so the LDS latency overlaps the step
+        float fill = kInf;
+        if constexpr (G > 1) {
+            if (wave > 0) fill = ring[wave - 1][(s + 1 - wave * (64 + kLag)) & (kPRing - 1)];
+        }
+        yv = lane_shift_down(yv, __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ycur), qs)));
         const int c = s - skew;
-        // columns before 0 only ever see +inf neighbours; columns past nb are
-        // never read back and never feed a column below nb
-        const float yv = b[c < 0 ? 0 : (c >= nb ? nb - 1 : c)];
         float diag = diag_in, up = up_in;
         const int off = rbase - c;
 #pragma unroll
@@ -83,20 +103,23 @@ __global__ __launch_bounds__(64 * G) void k_cost_matrix(const float *__restrict_
             float xe = x[h];
             if constexpr (BANDED) xe = (unsigned)(off + h + band) > (unsigned)(2 * band) ? kBig : xe;
             const float d = xe - yv;
-            const float v = fmaf(d, d, min3f(diag, up, O[h]));
-            diag = O[h];
+            const float v = fmaf(d, d, min3f(diag, up, Oi[h]));
+            diag = Oi[h];
             up = v;
-            O[h] = v;
-            zw[h * 64] = v;
+            Oo[h] = v;
         }
-        zw += zstep;
-        const float bottom = O[H - 1];
-        float fill = kInf;
+        if constexpr (H % 4 == 0) {
+#pragma unroll
+            for (int h = 0; h < H; h += 4)
+                *reinterpret_cast<float4 *>(zl + h) = make_float4(Oo[h], Oo[h + 1], Oo[h + 2], Oo[h + 3]);
+        } else {
+#pragma unroll
+            for (int h = 0; h < H; ++h) zl[h] = Oo[h];
+        }
+        zl += zstep;
+        const float bottom = Oo[H - 1];
         if constexpr (G > 1) {
             if (lane == 63 && wave < G - 1) ring[wave][c & (kPRing - 1)] = bottom;
-            // lane 0's up neighbour for step s+1: column s+1 - wave(64+kLag) of the
-            // wavefront above, written by it kLag steps ago (a barrier lies between)
-            if (wave > 0) fill = ring[wave - 1][(s + 1 - wave * (64 + kLag)) & (kPRing - 1)];
         }
         const float recv = lane_shift_down(bottom, fill);
         diag_in = up_in;
@@ -104,74 +127,119 @@ __global__ __launch_bounds__(64 * G) void k_cost_matrix(const float *__restrict_
         if constexpr (G > 1) {
             if ((s + 1) % kLag == 0) __syncthreads();
         }
+    };
+
+    // Blocks of 64 steps: the y block is consumed in registers while the next
+    // one loads (a value loaded in the inner loop would make every step wait
+    // for all earlier stores, which share the vector memory counter).
+    for (int s0 = 0; s0 < geo.steps; s0 += 64) {
+        const float ycur = ynext;
+        ynext = yblock(s0 + 64);
+        const int s1 = s0 + 64 < geo.steps ? s0 + 64 : geo.steps;
+        int s = s0;
+        for (; s + 1 < s1; s += 2) {
+            step(s, ycur, s - s0, A, B);
+            step(s + 1, ycur, s + 1 - s0, B, A);
+        }
+        if (s < s1) {  // odd step count: only in the last block
+            step(s, ycur, s - s0, A, B);
+#pragma unroll
+            for (int h = 0; h < H; ++h) A[h] = B[h];
+        }
     }
 }
 
 // One wavefront walks back from (n-1, m-1) to (0, 0): from each cell to the
 // predecessor with the smallest cumulative cost, ties in the order diagonal,
-// (i-1, j), (i, j-1).  The walk runs on 64x64 tiles of C staged in LDS with
-// the current cell at the tile's bottom-right corner; every tile allows at
-// least 63 steps.  Lane 0 walks and writes the path backwards; the wavefront
-// then reverses it in place.
+// (i-1, j), (i, j-1); on the first row or column only one predecessor exists
+// (the others are the +inf border) and the walk takes it outright, which also
+// keeps it inside the matrix when costs overflow or are NaN.
+//
+// The walk runs on 64x64 tiles of C with the current cell at the bottom-right
+// corner; each tile allows at least 63 moves.  Lane t loads tile row t (64
+// independent loads in flight) and the wavefront decides every cell's move in
+// parallel (the row above arrives by DPP): 2 bits per cell, bit 0 "row - 1",
+// bit 1 "column - 1", 0 where the walk must leave the tile (its first row or
+// column, where the move would need cells outside it) or has reached the
+// origin; 16 cells per register, 4 registers per lane.  A move is then a
+// register-indexed read, a lane read and a few scalar operations, no memory
+// access.  Lane (k mod 64) of two registers keeps the k-th cell of the path;
+// every 64 cells the wavefront stores them with one write.  The path is
+// produced backwards and reversed in place at the end.
+typedef unsigned MoveWords __attribute__((ext_vector_type(16)));  // register-indexed reads need >= 16 elements
+
 __global__ __launch_bounds__(64) void k_backtrack(const float *__restrict__ Z, const PathGeom geo, int n, int m,
                                                   int *__restrict__ path, int64_t *__restrict__ out_len,
                                                   float *__restrict__ out_cost) {
-    __shared__ float tile[64][65];
-    __shared__ int64_t st[3];
     const int lane = threadIdx.x;
-    int i = n - 1, j = m - 1;
-    int64_t k = 1;
-    if (lane == 0) {
-        path[0] = i;
-        path[1] = j;
-    }
+    int i = n - 1, j = m - 1;  // current cell (wave-uniform)
+    int pi = i, pj = j;        // lane kk holds cell kbase + kk until the flush
+    int64_t kbase = 0;
+    int kk = 1;
     while (i > 0 || j > 0) {
         const int i0 = i - 63, j0 = j - 63;
-        for (int q = 0; q < 64; ++q) tile[lane][q] = cell_at(Z, geo, i0 + lane, j0 + q);
-        __syncthreads();
-        if (lane == 0) {
-            int ta = 63, tb = 63;
-            while (ta > 0 && tb > 0 && (i > 0 || j > 0)) {
-                const float d = tile[ta - 1][tb - 1], u = tile[ta - 1][tb], l = tile[ta][tb - 1];
-                // on the first row or column only one predecessor exists (the
-                // others are the +inf border); taking it outright keeps the walk
-                // inside the matrix even when costs overflow or are NaN
-                if (i == 0) {
-                    --tb;
-                } else if (j == 0) {
-                    --ta;
-                } else if (d <= u && d <= l) {
-                    --ta;
-                    --tb;
-                } else if (u <= l) {
-                    --ta;
-                } else {
-                    --tb;
-                }
-                i = i0 + ta;
-                j = j0 + tb;
-                path[2 * k] = i;
-                path[2 * k + 1] = j;
-                ++k;
-            }
-            st[0] = i;
-            st[1] = j;
-            st[2] = k;
+        const int r = i0 + lane;
+        const int rc = r < 0 ? 0 : r;
+        // zindex(rr, cc) = zindex(rr, 0) + cc*S: a per-lane base plus a
+        // wave-uniform offset per tile column, whichever series the rows are
+        const int64_t S = (int64_t)geo.G * 64 * geo.H;
+        const float *__restrict__ zr = Z + (geo.swap ? rc * S : zindex(geo, rc, 0));
+        float v[64];
+        if (geo.swap) {
+#pragma unroll
+            for (int q = 0; q < 64; ++q) v[q] = zr[zindex(geo, j0 + q < 0 ? 0 : j0 + q, 0)];
+        } else {
+#pragma unroll
+            for (int q = 0; q < 64; ++q) v[q] = zr[(j0 + q < 0 ? 0 : j0 + q) * S];
         }
-        __syncthreads();
-        i = static_cast<int>(st[0]);
-        j = static_cast<int>(st[1]);
-        k = st[2];
-        __syncthreads();  // st is read by every lane before lane 0 writes it again
+#pragma unroll
+        for (int q = 0; q < 64; ++q) v[q] = (r < 0 || j0 + q < 0) ? kInf : v[q];
+        MoveWords mw = {};
+        float diag = lane_shift_down(v[0], kInf);
+#pragma unroll
+        for (int q = 1; q < 64; ++q) {
+            const float up = lane_shift_down(v[q], kInf), left = v[q - 1];
+            unsigned code = (diag <= up && diag <= left) ? 3u : (up <= left ? 1u : 2u);
+            code = r == 0 ? (j0 + q == 0 ? 0u : 2u) : (j0 + q == 0 ? 1u : code);  // C's first row / column
+            code = lane == 0 ? 0u : code;                                         // the tile's first row
+            mw[q >> 4] |= code << (2 * (q & 15));
+            diag = up;
+        }
+        int ta = 63, tb = 63;
+        for (;;) {
+            const unsigned word = mw[tb >> 4];
+            const unsigned code =
+                (static_cast<unsigned>(__builtin_amdgcn_readlane(static_cast<int>(word), ta)) >> (2 * (tb & 15))) & 3u;
+            if (code == 0u) break;
+            ta -= static_cast<int>(code & 1u);
+            tb -= static_cast<int>(code >> 1);
+            const bool mine = lane == kk;
+            pi = mine ? i0 + ta : pi;
+            pj = mine ? j0 + tb : pj;
+            if (++kk == 64) {
+                path[2 * (kbase + lane)] = pi;
+                path[2 * (kbase + lane) + 1] = pj;
+                kbase += 64;
+                kk = 0;
+            }
+        }
+        i = i0 + ta;
+        j = j0 + tb;
     }
+    if (lane < kk) {
+        path[2 * (kbase + lane)] = pi;
+        path[2 * (kbase + lane) + 1] = pj;
+    }
+    const int64_t k = kbase + kk;
+    __syncthreads();  // the stores above are visible to every lane of the workgroup
     for (int64_t p = lane; p < k / 2; p += 64) {
         const int64_t q = k - 1 - p;
-        const int pi = path[2 * p], pj = path[2 * p + 1];
-        const int qi = path[2 * q], qj = path[2 * q + 1];
-        path[2 * p] = qi;
-        path[2 * p + 1] = qj;
-        path[2 * q] = pi;
-        path[2 * q + 1] = pj;
+        const int a0 = path[2 * p], a1 = path[2 * p + 1];
+        const int b0 = path[2 * q], b1 = path[2 * q + 1];
+        path[2 * p] = b0;
+        path[2 * p + 1] = b1;
+        path[2 * q] = a0;
+        path[2 * q + 1] = a1;
     }
     if (lane == 0) {
         *out_len = k;
