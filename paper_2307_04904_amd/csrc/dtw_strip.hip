@@ -5,6 +5,8 @@
 // rule of the Introduction.
 #include "dtw_device.h"
 
+#include <type_traits>
+
 namespace dtwmi {
 namespace {
 
@@ -261,6 +263,113 @@ __device__ __forceinline__ void strip_item(const WaveItem it, const float *__res
     if (wave == wf && lane == lf) DI.out[it.slot] = ACC::result(res);
 }
 
+// Unwindowed strips, two columns per step.  Lane l of wavefront g handles
+// columns c0 = 2u - (m & 1) and c0 + 1, u = t - l - g(64+D), at step t (the
+// pairing puts the last column m-1 second in its pair; a column -1 reads the
+// +inf pad and stays +inf).  Within the step the two columns are evaluated
+// interleaved with a one-row lag -- cell (h, c0), then (h-1, c0+1) -- so each
+// lane runs two independent dependency chains, and the second column is
+// written over the first one's predecessor in place: the state is H cells
+// plus three, not 2H.  Both bottom cells go down one lane per step (two DPP
+// moves); between wavefronts both go through the LDS ring.
+template <class ACC, int H, int G>
+__device__ __forceinline__ void strip2_item(const WaveItem it, const float *__restrict__ ws,
+                                            const SeriesInfo *__restrict__ ser, const DatasetInfo *__restrict__ dsi,
+                                            typename ACC::T (*ring)[kRing]) {
+    using T = typename ACC::T;
+    constexpr int D = G > 1 ? kEpoch : 0;
+
+    const int lane = item_lane(it.ds) & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const DatasetInfo DI = dsi[it.ds];
+    const SeriesInfo sr = ser[DI.series_base + it.rows];
+    const SeriesInfo sc = ser[DI.series_base + it.cols];
+    const int n = sr.len, m = sc.len;
+    const float *__restrict__ xp = ws + sr.pstart;
+    const float *__restrict__ yp = ws + sc.pstart;
+    const int rbase = (wave * 64 + lane) * H;
+    const int shift = m & 1;
+    const int skew = lane + wave * (64 + D);  // u = t - skew
+    const int Lf = (n - 1) / H, wf = Lf >> 6, lf = Lf & 63, hf = (n - 1) - Lf * H;
+    const int tfinal = (m - 2 + shift) / 2 + lf + wf * (64 + D);  // step whose second column is m-1
+
+    float x[H];
+    T A[H];
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+        const int r = rbase + h;
+        const float v = xp[r < n ? r : n - 1];
+        x[h] = r < n ? v : 0.0f;  // rows past n never feed row n-1
+        A[h] = ACC::inf();
+    }
+    if constexpr (G > 1) {
+        for (int k = threadIdx.x; k < (G - 1) * kRing; k += 64 * G) ring[k / kRing][k % kRing] = ACC::inf();
+        __syncthreads();
+    }
+    // Row -1 as seen by lane 0 of wavefront 0: +inf, except c(0,0) = 0 of the
+    // 1-based recurrence, the diagonal of column 0.
+    const bool corner = lane == 0 && wave == 0;
+    T recv0 = (corner && shift) ? ACC::zero() : ACC::inf();   // bottom of column c0 from the lane above
+    T recv1 = ACC::inf();                                     // bottom of column c0 + 1
+    T prev1 = (corner && !shift) ? ACC::zero() : ACC::inf();  // bottom of column c0 - 1
+
+    auto col_of = [&](int t) { return 2 * (t - skew) - shift; };  // first column of step t
+    // y of column c: a single wavefront reads columns [-127, m+127] (inside
+    // the +inf pads); later wavefronts clamp into [-1, m]
+    auto yv = [&](int c) -> float {
+        if constexpr (G == 1) return yp[c];
+        return yp[c < -1 ? -1 : (c > m ? m : c)];
+    };
+    auto boundary = [&](int t, int k) -> T {  // lane 0's up value for column k of step t
+        if constexpr (G > 1) {
+            if (wave > 0) return ring[wave - 1][(col_of(t) + k) & (kRing - 1)];
+        }
+        return ACC::inf();
+    };
+    auto publish = [&](int t, const T &b0, const T &b1) {
+        if constexpr (G > 1) {
+            if (lane == 63 && wave < G - 1) {
+                const int c = col_of(t);
+                ring[wave][c & (kRing - 1)] = b0;
+                ring[wave][(c + 1) & (kRing - 1)] = b1;
+            }
+        }
+    };
+
+    const int c = col_of(0);
+    float y0 = yv(c), y1 = yv(c + 1);
+    for (int t = 0; t <= tfinal; ++t) {
+        const int cn = col_of(t + 1);
+        const float n0 = yv(cn), n1 = yv(cn + 1);
+        // column c0: diag = prev1 (row -1 of column c0-1), up = recv0; column c0+1: diag = recv0, up = recv1
+        T bm1 = ACC::inf(), bm2 = ACC::inf();
+#pragma unroll
+        for (int h = 0; h <= H; ++h) {
+            T bh = ACC::inf();
+            if (h < H) bh = ACC::cell(x[h], y0, h == 0 ? prev1 : A[h - 1], h == 0 ? recv0 : bm1, A[h]);
+            if (h >= 1) {
+                const int g = h - 1;
+                A[g] = ACC::cell(x[g], y1, g == 0 ? recv0 : bm2, g == 0 ? recv1 : A[g - 1 < 0 ? 0 : g - 1], bm1);
+            }
+            if (h < H) {
+                bm2 = bm1;
+                bm1 = bh;
+            }
+        }
+        // bm1 = column c0 row H-1, A[H-1] = column c0+1 row H-1
+        publish(t, bm1, A[H - 1]);
+        prev1 = recv1;
+        recv0 = lane_shift_down(bm1, boundary(t + 1, 0));
+        recv1 = lane_shift_down(A[H - 1], boundary(t + 1, 1));
+        y0 = n0;
+        y1 = n1;
+        if constexpr (G > 1) {
+            if ((t + 1) % kEpoch == 0) __syncthreads();
+        }
+    }
+    if (wave == wf && lane == lf) DI.out[it.slot] = ACC::result(pick<H>(A, hf));
+}
+
 template <class ACC, int H, int G, bool BANDED>
 __global__ __launch_bounds__(64 * G) void k_strip(const float *__restrict__ ws, const SeriesInfo *__restrict__ ser,
                                                   const DatasetInfo *__restrict__ dsi,
@@ -272,7 +381,13 @@ __global__ __launch_bounds__(64 * G) void k_strip(const float *__restrict__ ws, 
     for (;;) {
         if (queue) idx = next_item<G>(queue, &slot);
         if (idx >= n_items) break;
-        strip_item<ACC, H, G, BANDED>(items[idx], ws, ser, dsi, ring);
+        // unwindowed plain FP32 strips take two columns per step; the
+        // compensated and FP64 cells already hold enough independent work
+        // per cell (measured slower in the two-column form)
+        if constexpr (!BANDED && std::is_same<ACC, AccPlain>::value)
+            strip2_item<ACC, H, G>(items[idx], ws, ser, dsi, ring);
+        else
+            strip_item<ACC, H, G, BANDED>(items[idx], ws, ser, dsi, ring);
         if (!queue) break;
     }
 }
