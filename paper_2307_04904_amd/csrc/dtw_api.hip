@@ -105,7 +105,9 @@ struct WaveGroup {
     StripShape shape;  // G == 0: cyclic kernel with H = shape.H
     bool banded;
     int64_t begin, count;
-    int slots = 0;  // resident workgroups of the kernel (queue mode)
+    int slots = 0;           // resident workgroups of the kernel (queue mode)
+    int64_t band_cells = 0;  // admissible cells of the group's pairs
+    int64_t swept_cells = 0; // cells its kernel sweeps, padding included
 };
 
 
@@ -732,14 +734,20 @@ int plan_build(dtw_plan *plan_out, const dtw_dataset *ds, int32_t n_datasets, co
 
     // Group by kernel instance (H, G, banded); inside a group costlier pairs
     // first, groups in decreasing order of their costliest pair.
-    std::map<std::tuple<int, int, bool>, std::vector<std::pair<int64_t, WaveItem>>> wave_by_kind;
+    using Kind = std::tuple<int, int, bool>;  // H, G, banded
+    std::map<Kind, std::vector<std::pair<int64_t, WaveItem>>> wave_by_kind;
+    std::map<Kind, std::pair<int64_t, int64_t>> cells_by_kind;  // admissible, swept
     for (size_t k = 0; k < wpairs.size(); ++k) {
         const Choice c = choice[k];
         const WavePair &w = wpairs[k];
-        st.computed_cells += choice_steps_cells(c, w);
+        const int64_t swept = choice_steps_cells(c, w);
+        st.computed_cells += swept;
         st.n_cyclic_items += c.cyclic() ? 1 : 0;
-        wave_by_kind[std::make_tuple(c.H, c.G, c.cyclic() || w.b >= 0)].push_back(
-            {choice_cost(accum, c, w), make_item(c, w)});
+        const Kind kind = std::make_tuple(c.H, c.G, c.cyclic() || w.b >= 0);
+        wave_by_kind[kind].push_back({choice_cost(accum, c, w), make_item(c, w)});
+        auto &cells = cells_by_kind[kind];
+        cells.first += band_cells(w.n, w.m, w.b);
+        cells.second += swept;
     }
     std::vector<decltype(wave_by_kind)::iterator> order;
     for (auto it = wave_by_kind.begin(); it != wave_by_kind.end(); ++it) {
@@ -760,8 +768,9 @@ int plan_build(dtw_plan *plan_out, const dtw_dataset *ds, int32_t n_datasets, co
             return fail(DTW_ERR_UNSUPPORTED, "more than 2^31-1 work items for one kernel");
         }
         const StripShape sh{std::get<0>(it->first), std::get<1>(it->first)};
-        p->wave_groups.push_back(
-            WaveGroup{sh, std::get<2>(it->first), (int64_t)wave_items.size(), (int64_t)v.size(), 0});
+        const auto &cells = cells_by_kind[it->first];
+        p->wave_groups.push_back(WaveGroup{sh, std::get<2>(it->first), (int64_t)wave_items.size(), (int64_t)v.size(),
+                                           0, cells.first, cells.second});
         for (auto &e2 : v) wave_items.push_back(e2.second);
     }
     if (p->wave_groups.size() > (size_t)kMaxQueues) {
@@ -896,9 +905,12 @@ int dtw_plan_describe(dtw_plan p, char *buf, int64_t size, int64_t *needed) {
     j += "], \"wave_groups\": [";
     for (size_t k = 0; k < p->wave_groups.size(); ++k) {
         const WaveGroup &g = p->wave_groups[k];
-        snprintf(t, sizeof t, "%s{\"kernel\": \"%s\", \"banded\": %s, \"items\": %lld, \"grid\": %lld}",
+        snprintf(t, sizeof t,
+                 "%s{\"kernel\": \"%s\", \"banded\": %s, \"items\": %lld, \"grid\": %lld, \"band_cells\": %lld, "
+                 "\"swept_cells\": %lld}",
                  k ? ", " : "", choice_name(Choice{g.shape.H, g.shape.G}).c_str(), g.banded ? "true" : "false",
-                 (long long)g.count, (long long)(p->n_queue && g.slots > 0 ? std::min<int64_t>(g.slots, g.count) : g.count));
+                 (long long)g.count, (long long)(p->n_queue && g.slots > 0 ? std::min<int64_t>(g.slots, g.count) : g.count),
+                 (long long)g.band_cells, (long long)g.swept_cells);
         j += t;
     }
     j += "], \"tuned\": [";

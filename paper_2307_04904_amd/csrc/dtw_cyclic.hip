@@ -225,10 +225,11 @@ struct CycEntry {
     CycFn fn;
     SlotsFn slots;
 };
-const CycEntry kCyclic[] = {{1, &cyc_launch<1>, &cyc_slots<1>},    {2, &cyc_launch<2>, &cyc_slots<2>},
-                            {4, &cyc_launch<4>, &cyc_slots<4>},    {8, &cyc_launch<8>, &cyc_slots<8>},
-                            {12, &cyc_launch<12>, &cyc_slots<12>}, {16, &cyc_launch<16>, &cyc_slots<16>},
-                            {24, &cyc_launch<24>, &cyc_slots<24>}, {32, &cyc_launch<32>, &cyc_slots<32>}};
+#define DTWMI_CYC(H) {H, &cyc_launch<H>, &cyc_slots<H>}
+const CycEntry kCyclic[] = {DTWMI_CYC(1),  DTWMI_CYC(2),  DTWMI_CYC(3),  DTWMI_CYC(4),  DTWMI_CYC(6),
+                            DTWMI_CYC(8),  DTWMI_CYC(10), DTWMI_CYC(12), DTWMI_CYC(16), DTWMI_CYC(20),
+                            DTWMI_CYC(24), DTWMI_CYC(28), DTWMI_CYC(32)};
+#undef DTWMI_CYC
 
 // Grid of a launch: one workgroup per item, or with a queue the resident
 // workgroups (at most one per item).

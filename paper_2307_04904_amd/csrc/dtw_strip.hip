@@ -421,12 +421,17 @@ struct StripEntry {
 #define DTWMI_STRIP(A, ACC, H, G) {A, H, G, &strip_launch<ACC, H, G>, &strip_slots<ACC, H, G>}
 // Instantiated shapes, per accumulation mode in increasing row capacity 64*H*G.
 const StripEntry kStrips[] = {
-    DTWMI_STRIP(0, AccPlain, 1, 1),  DTWMI_STRIP(0, AccPlain, 2, 1),  DTWMI_STRIP(0, AccPlain, 4, 1),
-    DTWMI_STRIP(0, AccPlain, 8, 1),  DTWMI_STRIP(0, AccPlain, 12, 1), DTWMI_STRIP(0, AccPlain, 16, 1),
-    DTWMI_STRIP(0, AccPlain, 24, 1), DTWMI_STRIP(0, AccPlain, 32, 1), DTWMI_STRIP(0, AccPlain, 16, 2),
-    DTWMI_STRIP(0, AccPlain, 48, 1), DTWMI_STRIP(0, AccPlain, 24, 2), DTWMI_STRIP(0, AccPlain, 64, 1),
-    DTWMI_STRIP(0, AccPlain, 32, 2), DTWMI_STRIP(0, AccPlain, 32, 4), DTWMI_STRIP(0, AccPlain, 32, 8),
-    DTWMI_STRIP(0, AccPlain, 64, 8),
+    // plain FP32: every height up to 8, then steps of 2 to 16, of 4 to 32, of 8 to 64,
+    // so that a series of n points fills at least ~85% of its lanes' rows
+    DTWMI_STRIP(0, AccPlain, 1, 1),  DTWMI_STRIP(0, AccPlain, 2, 1),  DTWMI_STRIP(0, AccPlain, 3, 1),
+    DTWMI_STRIP(0, AccPlain, 4, 1),  DTWMI_STRIP(0, AccPlain, 5, 1),  DTWMI_STRIP(0, AccPlain, 6, 1),
+    DTWMI_STRIP(0, AccPlain, 7, 1),  DTWMI_STRIP(0, AccPlain, 8, 1),  DTWMI_STRIP(0, AccPlain, 10, 1),
+    DTWMI_STRIP(0, AccPlain, 12, 1), DTWMI_STRIP(0, AccPlain, 14, 1), DTWMI_STRIP(0, AccPlain, 16, 1),
+    DTWMI_STRIP(0, AccPlain, 20, 1), DTWMI_STRIP(0, AccPlain, 24, 1), DTWMI_STRIP(0, AccPlain, 28, 1),
+    DTWMI_STRIP(0, AccPlain, 32, 1), DTWMI_STRIP(0, AccPlain, 16, 2), DTWMI_STRIP(0, AccPlain, 40, 1),
+    DTWMI_STRIP(0, AccPlain, 48, 1), DTWMI_STRIP(0, AccPlain, 24, 2), DTWMI_STRIP(0, AccPlain, 56, 1),
+    DTWMI_STRIP(0, AccPlain, 64, 1), DTWMI_STRIP(0, AccPlain, 32, 2), DTWMI_STRIP(0, AccPlain, 32, 4),
+    DTWMI_STRIP(0, AccPlain, 32, 8), DTWMI_STRIP(0, AccPlain, 64, 8),
     DTWMI_STRIP(1, AccKahan, 1, 1),  DTWMI_STRIP(1, AccKahan, 2, 1),  DTWMI_STRIP(1, AccKahan, 4, 1),
     DTWMI_STRIP(1, AccKahan, 8, 1),  DTWMI_STRIP(1, AccKahan, 16, 1), DTWMI_STRIP(1, AccKahan, 16, 2),
     DTWMI_STRIP(1, AccKahan, 16, 4), DTWMI_STRIP(1, AccKahan, 16, 8), DTWMI_STRIP(1, AccKahan, 16, 16),
