@@ -21,8 +21,6 @@ namespace dtwmi {
 namespace {
 
 constexpr int kRowBlock = 64;   // rows of D per workgroup (one row per lane)
-constexpr int kMaxWaves = 4;    // wavefronts per row-sum workgroup, each with its own accumulators
-constexpr int kSumWaves = 1;    // wavefronts the launcher uses (measured: one per workgroup is fastest)
 constexpr int kReduce = 256;    // threads of the reduction kernels
 
 __device__ __forceinline__ float dist(const float *__restrict__ D, int i, int j, int N) {
@@ -30,61 +28,98 @@ __device__ __forceinline__ float dist(const float *__restrict__ D, int i, int j,
 }
 
 // P[split][i][J] = sum of D(i, j) over the columns j of this split's column
-// tiles with j != i and labels[j] == J.  Workgroup (row block, split) of W
-// wavefronts; wavefront w sweeps every W-th tile of the split, and its thread
-// t owns row i0 + t and K accumulators acc[w][J][t] in LDS (J uniform across
-// the wavefront, so the accesses are conflict-free); the W partial sums are
-// added in wavefront order at the end.  A column tile left of the diagonal
-// reads D(j, i0..i0+63): 64 consecutive entries of row j of the condensed
-// triangle, one coalesced load per column.  Right of the diagonal each thread
-// reads the 64 consecutive entries D(i, j0..j0+63) of its own row: every
-// cache line a wavefront touches is used whole over the tile.  Each tile's 64
-// labels are staged in LDS and its 64 values per thread loaded into registers
-// before any accumulation, so a tile's loads are all in flight at once.
-// Entries outside the matrix or on the diagonal contribute 0.
-__global__ __launch_bounds__(kRowBlock * kMaxWaves) void k_row_cluster_sums(const float *__restrict__ D, int N,
-                                                                            const int *__restrict__ labels, int K,
-                                                                            int tiles_per_split,
-                                                                            double *__restrict__ P) {
-    extern __shared__ double acc[];  // [W][K][64]
-    __shared__ int lab[kMaxWaves][kRowBlock];
-    const int t = threadIdx.x & (kRowBlock - 1);
-    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kRowBlock), W = blockDim.x / kRowBlock;
-    double *my = acc + (size_t)w * K * kRowBlock;
+// tiles with j != i and labels[j] == J.  Workgroup (row block, split) of one
+// wavefront: thread t owns row i0 + t and K <= 16 NV accumulators in registers.
+// A column's label is the same for every lane (one column per step of the
+// accumulation loop), so acc[label] is a register-indexed read-modify-write
+// on a wave-uniform index (s_set_gpr_idx); labels come in by scalar loads.
+// Each tile's values are loaded CH columns at a time, all in flight at once:
+//  * left of the diagonal, D(j, i) for a column j is 64 consecutive entries of
+//    row j of the condensed triangle, one coalesced load per column;
+//  * right of it, D(i, j) for a row i is 64 consecutive entries of row i:
+//    the wavefront first copies the tile row by row (one coalesced load per
+//    row, lane = column) into LDS and reads it back transposed (lane = row);
+//  * the diagonal tile reads entry by entry.
+// Entries outside the matrix or on the diagonal contribute 0.  Additions run
+// in column order, so the result does not depend on the schedule.
+typedef double Acc16 __attribute__((ext_vector_type(16)));  // register-indexed access needs <= 16 doubles
+
+// acc[l] += x for a wave-uniform l < 16 NV, over NV vectors of 16 accumulators.
+template <int NV>
+__device__ __forceinline__ void acc_add(Acc16 (&acc)[NV], int l, double x) {
+    if constexpr (NV == 1) {
+        acc[0][l] += x;
+    } else {
+        if (l < 16) {
+            acc[0][l] += x;
+        } else if (NV == 2 || l < 32) {
+            acc[1][l - 16] += x;
+        } else if (NV == 3 || l < 48) {
+            acc[NV > 2 ? 2 : 0][l - 32] += x;
+        } else {
+            acc[NV > 3 ? 3 : 0][l - 48] += x;
+        }
+    }
+}
+
+template <int NV, int CH>
+__global__ __launch_bounds__(kRowBlock) void k_row_cluster_sums(const float *__restrict__ D, int N,
+                                                                const int *__restrict__ labels, int K,
+                                                                int tiles_per_split, double *__restrict__ P) {
+    __shared__ float tile[kRowBlock][kRowBlock + 1];
+    Acc16 acc[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) acc[k] = Acc16{};
+    const int t = threadIdx.x;
     const int i0 = blockIdx.x * kRowBlock, i = i0 + t;
     const int split = blockIdx.y;
     const int n_tiles = (N + kRowBlock - 1) / kRowBlock;
     const int jt0 = split * tiles_per_split, jt1 = min(n_tiles, jt0 + tiles_per_split);
-    for (int J = 0; J < K; ++J) my[J * kRowBlock + t] = 0.0;
-    for (int jt = jt0 + w; jt < jt1; jt += W) {  // tiles of this wavefront: only wave-local LDS below
+    for (int jt = jt0; jt < jt1; ++jt) {
         const int j0 = jt * kRowBlock;
-        // lab[w] is this wavefront's own: its lanes run in lockstep and its LDS
-        // accesses complete in order, so only the compiler must keep the order
-        lab[w][t] = j0 + t < N ? labels[j0 + t] : 0;
-        __builtin_amdgcn_wave_barrier();
-        float v[kRowBlock];
-        if (j0 + kRowBlock <= i0) {  // left of the diagonal: D(j, i), consecutive in i
+        const bool left = j0 + kRowBlock <= i0, right = j0 >= i0 + kRowBlock;
+        if (right) {
+            const int j = j0 + t;
+            __builtin_amdgcn_wave_barrier();  // the previous tile's reads of `tile` are done
+            for (int r0 = 0; r0 < kRowBlock; r0 += 16) {
+                float w[16];
 #pragma unroll
-            for (int c = 0; c < kRowBlock; ++c) v[c] = i < N ? D[condensed_index(j0 + c, i, N)] : 0.0f;
-        } else if (j0 >= i0 + kRowBlock) {  // right of the diagonal: D(i, j), consecutive in j
-            const int64_t rb = i < N ? condensed_index(i, j0, N) : 0;
+                for (int r = 0; r < 16; ++r) {
+                    const int ir = i0 + r0 + r;  // wave-uniform row
+                    w[r] = (ir < N && j < N) ? D[condensed_index(ir, j0, N) + t] : 0.0f;
+                }
 #pragma unroll
-            for (int c = 0; c < kRowBlock; ++c) v[c] = (i < N && j0 + c < N) ? D[rb + c] : 0.0f;
-        } else {  // the diagonal tile
-#pragma unroll
-            for (int c = 0; c < kRowBlock; ++c) v[c] = (i < N && j0 + c < N) ? dist(D, i, j0 + c, N) : 0.0f;
+                for (int r = 0; r < 16; ++r) tile[r0 + r][t] = w[r];
+            }
+            __builtin_amdgcn_wave_barrier();
         }
+        for (int c0 = 0; c0 < kRowBlock; c0 += CH) {
+            float v[CH];
+            if (left) {  // D(j, i), consecutive in i
 #pragma unroll
-        for (int c = 0; c < kRowBlock; ++c) my[lab[w][c] * kRowBlock + t] += (double)v[c];
-        __builtin_amdgcn_wave_barrier();  // reads of lab[w] before the next tile's writes
+                for (int c = 0; c < CH; ++c) v[c] = i < N ? D[condensed_index(j0 + c0 + c, i, N)] : 0.0f;
+            } else if (right) {
+#pragma unroll
+                for (int c = 0; c < CH; ++c) v[c] = tile[t][c0 + c];
+            } else {  // the diagonal tile
+#pragma unroll
+                for (int c = 0; c < CH; ++c) {
+                    const int jc = j0 + c0 + c;
+                    v[c] = (i < N && jc < N) ? dist(D, i, jc, N) : 0.0f;
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < CH; ++c) {
+                const int jc = j0 + c0 + c;
+                const int lc = jc < N ? labels[jc] : 0;  // wave-uniform
+                acc_add<NV>(acc, lc, (double)v[c]);
+            }
+        }
     }
-    __syncthreads();  // every wavefront reaches this once
-    if (w == 0 && i < N)
-        for (int J = 0; J < K; ++J) {
-            double sum = 0.0;
-            for (int u = 0; u < W; ++u) sum += acc[((size_t)u * K + J) * kRowBlock + t];
-            P[((int64_t)split * N + i) * K + J] = sum;
-        }
+    if (i < N)
+#pragma unroll
+        for (int J = 0; J < 16 * NV; ++J)
+            if (J < K) P[((int64_t)split * N + i) * K + J] = acc[J / 16][J % 16];
 }
 
 // Fixed-order tree sum of one workgroup's values into out.
@@ -227,14 +262,13 @@ int dtw_silhouette(const float *D, int32_t N, const int32_t *labels, int32_t K, 
     if (std::count_if(sizes.begin(), sizes.end(), [](int32_t z) { return z > 0; }) < 2)
         return set_error(DTW_ERR_INVALID_ARG, "the silhouette needs at least two non-empty clusters");
 
-    // Wavefronts per workgroup: up to 4, with their accumulators within 64 KB of
-    // LDS; enough workgroups for ~8 wavefronts per SIMD, each wavefront with at
-    // least one column tile.
+    // Column tiles split so that there are ~2048 workgroups of one wavefront,
+    // each with at least one tile (more splits cost more in the per-series
+    // reduction of the partial sums than they gain here).
     const int row_blocks = (N + kRowBlock - 1) / kRowBlock;
     const int n_tiles = row_blocks;
-    const int waves = std::max(1, std::min(kSumWaves, 65536 / (K * kRowBlock * (int)sizeof(double))));
-    const int target_groups = 2048 / waves;
-    const int splits = std::max(1, std::min((n_tiles + waves - 1) / waves, (target_groups + row_blocks - 1) / row_blocks));
+    const int target_groups = 2048;
+    const int splits = std::max(1, std::min(n_tiles, (target_groups + row_blocks - 1) / row_blocks));
     const int tiles_per_split = (n_tiles + splits - 1) / splits;
     const int red_blocks = (N + kReduce - 1) / kReduce;
     const size_t o_sizes = 0, o_P = 256, bytes_P = (size_t)splits * N * K * sizeof(double);
@@ -250,8 +284,13 @@ int dtw_silhouette(const float *D, int32_t N, const int32_t *labels, int32_t K, 
     double *d_out = reinterpret_cast<double *>(base + o_out);
     e = hipMemcpyAsync(d_sizes, sizes.data(), K * sizeof(int32_t), hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return hip_err(e, "hipMemcpy (cluster sizes)");
-    hipLaunchKernelGGL(k_row_cluster_sums, dim3(row_blocks, splits), dim3(kRowBlock * waves),
-                       (size_t)waves * K * kRowBlock * sizeof(double), s, D, N, labels, K, tiles_per_split, d_P);
+    static_assert(kSilhouetteMaxK <= 64, "four vectors of 16 accumulators");
+    if (K <= 16)
+        hipLaunchKernelGGL((k_row_cluster_sums<1, 64>), dim3(row_blocks, splits), dim3(kRowBlock), 0, s, D, N, labels,
+                           K, tiles_per_split, d_P);
+    else
+        hipLaunchKernelGGL((k_row_cluster_sums<4, 16>), dim3(row_blocks, splits), dim3(kRowBlock), 0, s, D, N, labels,
+                           K, tiles_per_split, d_P);
     if ((e = hipGetLastError()) != hipSuccess) return hip_err(e, "row-sum kernel launch");
     hipLaunchKernelGGL(k_silhouette_rows, dim3(red_blocks), dim3(kReduce), 0, s, d_P, splits, N, K, labels, d_sizes,
                        s_out, d_part);
