@@ -146,7 +146,9 @@ int dtw_plan_create(dtw_plan *plan, const dtw_dataset *ds, int32_t n_datasets,
  * Enqueue one full evaluation (staging of the inputs into the padded FP32
  * workspace, then every DP kernel) on `stream` (hipStream_t, NULL = default).
  * Allocates nothing and never synchronises, so it may be captured into a HIP
- * graph.  Results are valid after the stream is synchronised.  Executions of
+ * graph: kernel groups of different instances run concurrently on up to four
+ * streams the plan owns, forked from `stream` and joined back into it by
+ * events.  Results are valid after the stream is synchronised.  Executions of
  * one plan on different streams must not overlap (they share the workspace).
  */
 int dtw_plan_execute(dtw_plan plan, void *stream);

@@ -301,7 +301,14 @@ struct dtw_plan_s {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     bool timed_once = false;
     std::vector<TunedBucket> tuned;
+    // Wavefront groups run on up to kAuxStreams streams of the plan, forked
+    // from and joined back to the caller's stream, so that one group's last
+    // workgroups overlap the next group's first.
+    int n_aux = 0;
+    hipStream_t aux[4] = {};
+    hipEvent_t fork_ev = nullptr, join_ev[4] = {};
 };
+constexpr int kAuxStreams = 4;
 
 namespace {
 
@@ -341,6 +348,11 @@ void destroy_plan(dtw_plan p) {
     if (p->dev_block) (void)hipFree(p->dev_block);
     if (p->ev0) (void)hipEventDestroy(p->ev0);
     if (p->ev1) (void)hipEventDestroy(p->ev1);
+    if (p->fork_ev) (void)hipEventDestroy(p->fork_ev);
+    for (int a = 0; a < kAuxStreams; ++a) {
+        if (p->join_ev[a]) (void)hipEventDestroy(p->join_ev[a]);
+        if (p->aux[a]) (void)hipStreamDestroy(p->aux[a]);
+    }
     delete p;
 }
 
@@ -800,6 +812,18 @@ int plan_build(dtw_plan *plan_out, const dtw_dataset *ds, int32_t n_datasets, co
             return hip_fail(e, "hipEventCreate");
         }
     }
+    if (p->wave_groups.size() > 1) {  // default-priority streams, events without timing
+        p->n_aux = std::min<int>(kAuxStreams, (int)p->wave_groups.size());
+        e = hipEventCreateWithFlags(&p->fork_ev, hipEventDisableTiming);
+        for (int a = 0; a < p->n_aux && e == hipSuccess; ++a) {
+            e = hipStreamCreateWithFlags(&p->aux[a], hipStreamNonBlocking);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&p->join_ev[a], hipEventDisableTiming);
+        }
+        if (e != hipSuccess) {
+            destroy_plan(p);
+            return hip_fail(e, "plan stream set-up");
+        }
+    }
     *plan_out = p;
     return DTW_OK;
 }
@@ -859,15 +883,26 @@ int dtw_plan_execute(dtw_plan p, void *stream) {
         e = launch_lane(g.W, p->ws, p->d_ser, p->d_ds, p->d_lane + g.begin, p->d_partner, (unsigned)g.count, s);
         if (e != hipSuccess) return hip_fail(e, "lane-band kernel launch");
     }
+    // Wavefront groups: forked over the plan's streams (round robin, costliest
+    // group first), then joined back into `s`.
+    if (p->n_aux && (e = hipEventRecord(p->fork_ev, s)) != hipSuccess) return hip_fail(e, "hipEventRecord (fork)");
+    for (int a = 0; a < p->n_aux; ++a)
+        if ((e = hipStreamWaitEvent(p->aux[a], p->fork_ev, 0)) != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
+    int k = 0;
     for (const WaveGroup &g : p->wave_groups) {
         unsigned *queue = p->d_queue ? p->d_queue + q++ : nullptr;
+        hipStream_t gs = p->n_aux ? p->aux[k++ % p->n_aux] : s;
         if (g.shape.G == 0)
             e = launch_cyclic(g.shape.H, p->ws, p->d_ser, p->d_ds, p->d_wave + g.begin, (unsigned)g.count, queue,
-                              g.slots, s);
+                              g.slots, gs);
         else
             e = launch_strip(p->accum, g.shape, g.banded, p->ws, p->d_ser, p->d_ds, p->d_wave + g.begin,
-                             (unsigned)g.count, queue, g.slots, s);
+                             (unsigned)g.count, queue, g.slots, gs);
         if (e != hipSuccess) return hip_fail(e, "wavefront kernel launch");
+    }
+    for (int a = 0; a < p->n_aux; ++a) {
+        if ((e = hipEventRecord(p->join_ev[a], p->aux[a])) != hipSuccess) return hip_fail(e, "hipEventRecord (join)");
+        if ((e = hipStreamWaitEvent(s, p->join_ev[a], 0)) != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
     }
     if (p->ev1) {
         if ((e = hipEventRecord(p->ev1, s)) != hipSuccess) return hip_fail(e, "hipEventRecord");

@@ -13,8 +13,9 @@
 // lengths, narrow band), dtw_strip.hip (one pair per workgroup, rows of the
 // shorter series in lane strips), dtw_cyclic.hip (one pair per wavefront,
 // blocks of the longer series cycling over the lanes); dtw_stage.hip stages
-// the inputs.  This header holds the device helpers they share.  Not part of
-// the public ABI.
+// the inputs; dtw_path.hip keeps the whole matrix of one pair for its warping
+// path and dtw_cluster.hip scores clusterings from D.  This header holds the
+// device helpers they share.  Not part of the public ABI.
 #pragma once
 
 #include "dtw_internal.h"

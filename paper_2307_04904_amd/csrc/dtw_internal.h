@@ -1,5 +1,6 @@
-// Internal layout shared by the host planner (dtw_api.hip) and the kernels
-// (dtw_kernels.hip).  Not part of the public ABI.
+// Internal layout shared by the host planner (dtw_api.hip) and the kernel
+// sources (dtw_stage.hip, dtw_lane.hip, dtw_strip.hip, dtw_cyclic.hip,
+// dtw_cluster.hip, dtw_path.hip).  Not part of the public ABI.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -59,7 +60,7 @@ struct WaveItem {
     int64_t slot;
 };
 
-// Kernel launchers (dtw_kernels.hip).  All asynchronous on `stream`.
+// Kernel launchers (one kernel source each).  All asynchronous on `stream`.
 // Wavefront launchers take the item count and a queue counter: with queue == nullptr
 // the grid has one workgroup per item; otherwise min(items, slots) resident
 // workgroups pull items from the counter, which must be zero at launch
