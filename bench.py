@@ -183,6 +183,25 @@ def cpu_baseline(dsets, gpu_outs, target_s, pair_list=None):
         "mean_rel_err": float(rel.mean()) if rel.size else 0.0, "zero_mismatch": zero_bad}
 
 
+def quantisation_error(dsets, dsets_f32, gpu_outs, n_pairs=64):
+    """GPU results on 16-bit storage against the FP64 oracle on the FP32 source
+    values (reported, not gated): what the 8- or 11-bit input rounding costs."""
+    import oracle
+    from paper_2307_04904_amd import synth
+    ds, src = dsets[0], dsets_f32[0]
+    rng = np.random.default_rng(54321)
+    i = rng.integers(0, ds.N, size=4 * n_pairs)
+    j = rng.integers(0, ds.N, size=4 * n_pairs)
+    keep = i != j
+    a = np.minimum(i, j)[keep][:n_pairs].astype(np.int32)
+    b = np.maximum(i, j)[keep][:n_pairs].astype(np.int32)
+    ref, _ = oracle.dtw_pairs(synth.stored_as_f64(src), src.offsets, src.lengths, a, b, src.window)
+    k = a.astype(np.int64) * ds.N - a.astype(np.int64) * (a + 1) // 2 + (b - a - 1)
+    g = gpu_outs[0][k].astype(np.float64)
+    rel = np.abs(g - ref) / ref
+    return {"pairs": int(len(a)), "max_rel_err": float(rel.max()), "mean_rel_err": float(rel.mean())}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -346,6 +365,9 @@ def main(argv=None):
         base, check = cpu_baseline(dsets, [o.cpu().numpy() for o in outs], args.cpu_seconds, pair_list)
         line["cpu_baseline"] = base
         line["gpu_vs_oracle_on_sample"] = check
+        if dsets[0].dtype != "f32" and len(dsets) == 1:
+            line["gpu_vs_oracle_on_fp32_source"] = quantisation_error(
+                dsets, make_datasets(args.workload, "f32"), [o.cpu().numpy() for o in outs])
     plan.destroy()
     print(json.dumps(line), flush=True)
     return 0
