@@ -48,6 +48,26 @@ __device__ __forceinline__ void cyc_setup(CycLane<H> &c, typename XVec<H>::T &xr
     c.phi = (c.g > 0 && r0 < n) ? min(m - 1, r0 - 1 + b) : -1;
 }
 
+// Move this lane to block c.g + 64 at a block switch.  Its rows start past
+// the window (r > b for every block g >= 64 when 64(H+1) >= 2b+H), so x is
+// kBig and the entry events admit them; rows past n read the +inf pad after
+// the series, whose cells never feed row n-1.
+template <int H>
+__device__ __forceinline__ void cyc_next_block(CycLane<H> &c, typename XVec<H>::T &xr, typename XVec<H>::T &x,
+                                               const float *__restrict__ xp, int n, int m, int b) {
+    c.g += 64;
+    const int r0 = c.g * H;
+    const float *__restrict__ xb = xp + (r0 < n ? r0 : n);
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+        xr[h] = xb[h];
+        x[h] = kBig;
+    }
+    c.gend = r0 < n ? min(m - 1, r0 + H - 1 + b) + c.g : 0x7fffffff;
+    c.yb = r0 < n ? c.g : (1 << 29);
+    c.phi = r0 < n ? min(m - 1, r0 - 1 + b) : -1;
+}
+
 // Row events of step s (wave-uniform: one lane per event).  Entry of row
 // qH+h at column qH+h-b, exit after column qH+h+b.  Only two tests are needed:
 //  * entries stop after row n-1 (s_last): in a pair with at most 64 blocks the
@@ -97,14 +117,15 @@ __device__ __forceinline__ void cyc_step(int s, CycLane<H> &c, typename XVec<H>:
                                          const float *__restrict__ xp, const float *__restrict__ yp, int lane,
                                          int n, int m, int b, int s_last) {
     if (s > c.gend) {  // this lane's block left the window: take block g+64
-        c.g += 64;
-        cyc_setup<H>(c, xr, x, xp, n, m, b);
+        cyc_next_block<H>(c, xr, x, xp, n, m, b);
         y0 = cyc_y(yp, s - c.yb);
         y1 = cyc_y(yp, s + 1 - c.yb);
         y2 = cyc_y(yp, s + 2 - c.yb);
         y3 = cyc_y(yp, s + 3 - c.yb);
-#pragma unroll
-        for (int h = 0; h < H; ++h) O[h] = kInf;
+        // Row 0 may be admitted at this very step (when 64(H+1) = 2b+H), so
+        // its left neighbour must be +inf now; rows below are admitted at
+        // least one step later and their kBig cells of the steps before are +inf.
+        O[0] = kInf;
         // The neighbour lane already holds block g-1 (g the new block), so the
         // values it sent in the last two steps are row gH-1 at this step's
         // column and at the one before; keep those that row's window admits (a
