@@ -19,78 +19,84 @@ namespace {
 // step.  Idle lanes sweep only while blocks are active instead of the whole
 // rectangle, which is what matters when the window is much narrower than the
 // pair: the in-window cells are a diagonal strip of the rectangle.
-// A received boundary value is replaced by +inf past the previous block's
-// window (its lane may already work on another block); window edges inside a
-// block use the row events above (exit events of a block's last row are not
-// needed: that row leaves the window when the block ends).
+//
+// The window needs no masking of whole rows.  An admissible cell (i,j) reads
+// two cells that can lie outside the window: its left neighbour (i,j-1) when
+// i-j = b and its upper neighbour (i-1,j) when j-i = b; every other cell
+// outside the window feeds only cells outside it.  So the kernel computes the
+// cells of a block's rows before they enter the window with their real x
+// values (the results are never read), and only
+//  * at the entry of row i (column i-b) sets that row's left value to +inf;
+//  * at the exit of row i (column i+b+1) sets x_i to kBig, so that the row's
+//    cells from there on overflow to +inf and the row below reads +inf;
+//  * replaces a received boundary value by +inf past the previous block's
+//    window (its last row exits there; its lane may already work on another
+//    block).
+// Register vector of a block's H rows (x, and the two column buffers), with a
+// wave-uniform runtime index turned into one indexed register move
+// (s_set_gpr_idx): the compiler does that for vectors of more than 8 elements
+// and expands smaller ones into a compare and a select per element, so small
+// blocks get 9 elements.
 template <int H>
-struct CycLane {  // the block a lane of a cyclic strip works on
-    int g, gend, phi;
-    int yb;  // y column of step s is s - yb: g, or far to the left once no block is left
+struct CycVec {
+    static constexpr int W = H <= 8 ? 9 : (H <= 12 ? H : (H <= 16 ? 16 : H));
+    typedef float T __attribute__((ext_vector_type(W)));
 };
 
-// Load block c.g of the pair into this lane (rows past n get x = 1e30).
 template <int H>
-__device__ __forceinline__ void cyc_setup(CycLane<H> &c, typename XVec<H>::T &xr, typename XVec<H>::T &x,
-                                          const float *__restrict__ xp, int n, int m, int b) {
-    const int r0 = c.g * H;
-    // rows [r0, r0+H) read from min(r0, n): at most H-1 < kPad past the end
-    const float *__restrict__ xb = xp + (r0 < n ? r0 : n);
-#pragma unroll
-    for (int h = 0; h < H; ++h) {
-        const int r = r0 + h;
-        const float v = xb[h];
-        xr[h] = r < n ? v : 0.0f;
-        x[h] = (r < n && r - b <= 0) ? v : kBig;
-    }
-    c.gend = r0 < n ? min(m - 1, r0 + H - 1 + b) + c.g : 0x7fffffff;
-    c.yb = r0 < n ? c.g : (1 << 29);
-    c.phi = (c.g > 0 && r0 < n) ? min(m - 1, r0 - 1 + b) : -1;
-}
+struct CycLane {  // the block a lane of a cyclic strip works on
+    int g;     // block index
+    int gend;  // last step of block g, or INT_MAX when no block g+64 follows it
+    int tphi;  // from step tphi+1 on, the boundary row received lies past its window
+    const float *__restrict__ yl;  // y column of step s: yl[s]
+};
 
-// Move this lane to block c.g + 64 at a block switch.  Its rows start past
-// the window (r > b for every block g >= 64 when 64(H+1) >= 2b+H), so x is
-// kBig and the entry events admit them; rows past n read the +inf pad after
-// the series, whose cells never feed row n-1.
+// Load block c.g into this lane: x of its rows (rows past n read the +inf pad
+// after the series; their cells never feed row n-1), the step its window ends,
+// the masking step of its boundary row and its y pointer.  y is read at
+// columns s - g without a clamp: every lane reads between column -63 (a block
+// starts at most 63 steps before its first column) and m+66 (no lane holds a
+// block more than 63 below the last one, which ends at step m-1+Qf), inside
+// the +inf pads of the staged series.
 template <int H>
-__device__ __forceinline__ void cyc_next_block(CycLane<H> &c, typename XVec<H>::T &xr, typename XVec<H>::T &x,
-                                               const float *__restrict__ xp, int n, int m, int b) {
-    c.g += 64;
+__device__ __forceinline__ void cyc_block(CycLane<H> &c, typename CycVec<H>::T &x, const float *__restrict__ xp,
+                                          const float *__restrict__ yp, int n, int m, int b, int Qf) {
     const int r0 = c.g * H;
     const float *__restrict__ xb = xp + (r0 < n ? r0 : n);
 #pragma unroll
-    for (int h = 0; h < H; ++h) {
-        xr[h] = xb[h];
-        x[h] = kBig;
-    }
-    c.gend = r0 < n ? min(m - 1, r0 + H - 1 + b) + c.g : 0x7fffffff;
-    c.yb = r0 < n ? c.g : (1 << 29);
-    c.phi = r0 < n ? min(m - 1, r0 - 1 + b) : -1;
+    for (int h = 0; h < H; ++h) x[h] = xb[h];
+    const bool live = r0 < n;
+    c.gend = (live && c.g + 64 <= Qf) ? min(m - 1, r0 + H - 1 + b) + c.g : 0x7fffffff;
+    c.tphi = ((c.g > 0 && live) ? min(m - 1, r0 - 1 + b) : -1) + c.g;
+    c.yl = yp - c.g;
 }
 
 // Row events of step s (wave-uniform: one lane per event).  Entry of row
-// qH+h at column qH+h-b, exit after column qH+h+b.  Only two tests are needed:
+// qH+h at column qH+h-b, exit after column qH+h+b.  The tests:
 //  * entries stop after row n-1 (s_last): in a pair with at most 64 blocks the
 //    band may be wide, and an entry of a block past n would land on the lane
 //    still holding block q-64;
-//  * exits need q >= 0 (q & 63 of a negative q names a lane with a live block).
-// Other spurious events are harmless: entries at columns <= 0 repeat what the
-// block set-up did (only blocks q < 64 have such rows when 64(H+1) >= 2b+H);
-// rows past n never feed row n-1; an exit that comes after its lane moved to
-// block q+64 precedes the entry of the same row there by at least one step.
+//  * exits need q >= 0 (q & 63 of a negative q names a lane with a live block)
+//    and a column before m: an exit past the last column would land on the
+//    lane's next block, whose rows keep their x from then on.
+// Other spurious events are harmless: entries at columns <= 0 find the +inf
+// the block started with; rows past n never feed row n-1.  Exits of a block's
+// last row are not needed: that row leaves the window when the block ends.
+// With 64(H+1) = 2b+H the entry of row qH is the step block q starts on; the
+// block switch comes first.
 template <int H>
-__device__ __forceinline__ void cyc_events(int s, RowCounter &en, RowCounter &ex, typename XVec<H>::T &x,
-                                           const typename XVec<H>::T &xr, int lane, int s_last) {
+__device__ __forceinline__ void cyc_events(int s, RowCounter &en, RowCounter &ex, typename CycVec<H>::T &x,
+                                           typename CycVec<H>::T &O, int lane, int s_last, int m) {
     // The empty asm statements keep each move a one-lane branch: without them
     // the compiler turns it into a select of the whole register vector.
     if (en.h < H && s <= s_last) {
         if (lane == (en.q & 63)) {
             asm volatile("");
-            x[en.h] = xr[en.h];
+            O[en.h] = kInf;
         }
     }
     en.advance<H>();
-    if (ex.h <= H - 2 && ex.q >= 0) {
+    if (ex.h <= H - 2 && ex.q >= 0 && s - ex.q < m) {
         if (lane == (ex.q & 63)) {
             asm volatile("");
             x[ex.h] = kBig;
@@ -99,44 +105,39 @@ __device__ __forceinline__ void cyc_events(int s, RowCounter &en, RowCounter &ex
     ex.advance<H>();
 }
 
-// y at column col, read from the +inf pad at -1 for columns left of the series.
-// No upper clamp: a lane reads at most 4 columns past m (steps prefetched
-// beyond its block's last step), well inside the pad, and a lane without a
-// block reads with yb far to the right of s.
-__device__ __forceinline__ float cyc_y(const float *__restrict__ yp, int col) {
-    return yp[col < -1 ? -1 : col];
-}
-
 // One step.  y0..y3 hold (or are loading) y at this lane's columns of steps
 // s..s+3; a block switch moves the columns by -64, so it reloads them.
 template <int H>
-__device__ __forceinline__ void cyc_step(int s, CycLane<H> &c, typename XVec<H>::T &xr, typename XVec<H>::T &x,
-                                         float (&O)[H], float (&N)[H], float &up_in, float &diag_in,
-                                         float &raw_up, float &raw_diag, RowCounter &en, RowCounter &ex,
-                                         float &y0, float &y1, float &y2, float &y3,
-                                         const float *__restrict__ xp, const float *__restrict__ yp, int lane,
-                                         int n, int m, int b, int s_last) {
+__device__ __forceinline__ void cyc_step(int s, CycLane<H> &c, typename CycVec<H>::T &x, typename CycVec<H>::T &O,
+                                         typename CycVec<H>::T &N, float &up_in, float &diag_in, float &raw_up,
+                                         float &raw_diag, RowCounter &en, RowCounter &ex, float &y0, float &y1,
+                                         float &y2, float &y3, const float *__restrict__ xp,
+                                         const float *__restrict__ yp, int lane, int n, int m, int b, int Qf,
+                                         int s_last) {
     if (s > c.gend) {  // this lane's block left the window: take block g+64
-        cyc_next_block<H>(c, xr, x, xp, n, m, b);
-        y0 = cyc_y(yp, s - c.yb);
-        y1 = cyc_y(yp, s + 1 - c.yb);
-        y2 = cyc_y(yp, s + 2 - c.yb);
-        y3 = cyc_y(yp, s + 3 - c.yb);
+        c.g += 64;
+        cyc_block<H>(c, x, xp, yp, n, m, b, Qf);
+        y0 = c.yl[s];
+        y1 = c.yl[s + 1];
+        y2 = c.yl[s + 2];
+        y3 = c.yl[s + 3];
+        // Wait for these loads here (vmcnt 0): x is read in this step, and
+        // without the wait the compiler, merging this rare path with the
+        // common one, would wait for every load in flight at every step.
+        __builtin_amdgcn_s_waitcnt(0x0F70);
         // Row 0 may be admitted at this very step (when 64(H+1) = 2b+H), so
-        // its left neighbour must be +inf now; rows below are admitted at
-        // least one step later and their kBig cells of the steps before are +inf.
+        // its left neighbour must be +inf now; the other rows get theirs at
+        // their entries.
         O[0] = kInf;
         // The neighbour lane already holds block g-1 (g the new block), so the
         // values it sent in the last two steps are row gH-1 at this step's
         // column and at the one before; keep those that row's window admits (a
         // path along the band edge runs through them when the switch comes one
         // step before the new block's first admissible column).
-        const int col0 = s - c.g;
-        up_in = col0 > c.phi ? kInf : raw_up;
-        diag_in = col0 - 1 > c.phi ? kInf : raw_diag;
+        up_in = s > c.tphi ? kInf : raw_up;
+        diag_in = s - 1 > c.tphi ? kInf : raw_diag;
     }
-    cyc_events<H>(s, en, ex, x, xr, lane, s_last);
-    const int col = s - c.g;
+    cyc_events<H>(s, en, ex, x, O, lane, s_last, m);
     const float yv = y0;
     float diag = diag_in, up = up_in;
 #pragma unroll
@@ -153,13 +154,13 @@ __device__ __forceinline__ void cyc_step(int s, CycLane<H> &c, typename XVec<H>:
     raw_diag = raw_up;
     raw_up = recv;
     diag_in = up_in;
-    up_in = (col + 1 > c.phi) ? kInf : recv;  // past the previous block's window
+    up_in = s < c.tphi ? recv : kInf;  // past the previous block's window
 }
 
 template <int H>
 __device__ __forceinline__ void cyc_item(const WaveItem it, const float *__restrict__ ws,
                                          const SeriesInfo *__restrict__ ser, const DatasetInfo *__restrict__ dsi) {
-    typedef typename XVec<H>::T xvec;
+    typedef typename CycVec<H>::T xvec;
     const int lane = item_lane(it.ds);
     const DatasetInfo DI = dsi[it.ds];
     const SeriesInfo sr = ser[DI.series_base + it.rows];
@@ -173,11 +174,10 @@ __device__ __forceinline__ void cyc_item(const WaveItem it, const float *__restr
 
     CycLane<H> c;
     c.g = lane;
-    xvec xr, x;
-    cyc_setup<H>(c, xr, x, xp, n, m, b);
-    float A[H], Bv[H];
+    xvec x, A, Bv;
+    cyc_block<H>(c, x, xp, yp, n, m, b, Qf);
 #pragma unroll
-    for (int h = 0; h < H; ++h) {
+    for (int h = 0; h < CycVec<H>::W; ++h) {
         A[h] = kInf;
         Bv[h] = kInf;
     }
@@ -188,27 +188,39 @@ __device__ __forceinline__ void cyc_item(const WaveItem it, const float *__restr
     en.init<H>(b);
     ex.init<H>(-b - 1);
 
+    // Four steps per iteration, so that the y prefetch registers rotate by
+    // name instead of by copies.
     int s = 0;
-    float y0 = cyc_y(yp, -c.yb), y1 = cyc_y(yp, 1 - c.yb), y2, y3, y4;
-    for (; s + 2 <= sfinal + 1; s += 2) {
-        // loads for the next two steps go out before this pair of steps
-        y2 = cyc_y(yp, s + 2 - c.yb);
-        y3 = cyc_y(yp, s + 3 - c.yb);
-        cyc_step<H>(s, c, xr, x, A, Bv, up_in, diag_in, raw_up, raw_diag, en, ex, y0, y1, y2, y3, xp, yp, lane, n,
-                    m, b, s_last);
-        cyc_step<H>(s + 1, c, xr, x, Bv, A, up_in, diag_in, raw_up, raw_diag, en, ex, y1, y2, y3, y4, xp, yp, lane,
-                    n, m, b, s_last);
-        y0 = y2;
-        y1 = y3;
+    float q0 = c.yl[0], q1 = c.yl[1], q2, q3;
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // x in place before the loop (see the block switch)
+    for (; s + 3 <= sfinal; s += 4) {
+        q2 = c.yl[s + 2];
+        q3 = c.yl[s + 3];
+        cyc_step<H>(s, c, x, A, Bv, up_in, diag_in, raw_up, raw_diag, en, ex, q0, q1, q2, q3, xp, yp, lane, n, m, b,
+                    Qf, s_last);
+        cyc_step<H>(s + 1, c, x, Bv, A, up_in, diag_in, raw_up, raw_diag, en, ex, q1, q2, q3, q0, xp, yp, lane, n,
+                    m, b, Qf, s_last);
+        q0 = c.yl[s + 4];
+        q1 = c.yl[s + 5];
+        cyc_step<H>(s + 2, c, x, A, Bv, up_in, diag_in, raw_up, raw_diag, en, ex, q2, q3, q0, q1, xp, yp, lane, n,
+                    m, b, Qf, s_last);
+        cyc_step<H>(s + 3, c, x, Bv, A, up_in, diag_in, raw_up, raw_diag, en, ex, q3, q0, q1, q2, xp, yp, lane, n,
+                    m, b, Qf, s_last);
     }
-    float res;
-    if (s <= sfinal) {
-        cyc_step<H>(s, c, xr, x, A, Bv, up_in, diag_in, raw_up, raw_diag, en, ex, y0, y1, y2, y3, xp, yp, lane, n,
-                    m, b, s_last);
-        res = pick<H>(Bv, hf);
-    } else {
-        res = pick<H>(A, hf);
+    const int rem = sfinal + 1 - s;  // 0..3 steps left
+    if (rem >= 1) {
+        q2 = c.yl[s + 2];
+        q3 = c.yl[s + 3];
+        cyc_step<H>(s, c, x, A, Bv, up_in, diag_in, raw_up, raw_diag, en, ex, q0, q1, q2, q3, xp, yp, lane, n, m, b,
+                    Qf, s_last);
     }
+    if (rem >= 2)
+        cyc_step<H>(s + 1, c, x, Bv, A, up_in, diag_in, raw_up, raw_diag, en, ex, q1, q2, q3, q0, xp, yp, lane, n,
+                    m, b, Qf, s_last);
+    if (rem >= 3)
+        cyc_step<H>(s + 2, c, x, A, Bv, up_in, diag_in, raw_up, raw_diag, en, ex, q2, q3, q0, q1, xp, yp, lane, n,
+                    m, b, Qf, s_last);
+    const float res = (rem & 1) ? Bv[hf] : A[hf];
     if (lane == (Qf & 63)) DI.out[it.slot] = res;
 }
 
