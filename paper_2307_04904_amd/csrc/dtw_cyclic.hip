@@ -48,6 +48,8 @@ struct CycLane {  // the block a lane of a cyclic strip works on
     int g;     // block index
     int gend;  // last step of block g, or INT_MAX when no block g+64 follows it
     int tphi;  // from step tphi+1 on, the boundary row received lies past its window
+    int E, emax;  // row h <= emax of the block enters the window at step E + h
+    int X, xmax;  // row h <= xmax leaves it at step X + h (x becomes kBig)
     const float *__restrict__ yl;  // y column of step s: yl[s]
 };
 
@@ -69,40 +71,42 @@ __device__ __forceinline__ void cyc_block(CycLane<H> &c, typename CycVec<H>::T &
     c.gend = (live && c.g + 64 <= Qf) ? min(m - 1, r0 + H - 1 + b) + c.g : 0x7fffffff;
     c.tphi = ((c.g > 0 && live) ? min(m - 1, r0 - 1 + b) : -1) + c.g;
     c.yl = yp - c.g;
+    // Row r0+h enters at column r0+h-b, i.e. step g(H+1)+h-b, for rows before
+    // n (rows past n never feed row n-1); it leaves after column r0+h+b, at
+    // step g(H+1)+h+b+1, for h <= H-2 (the last row is masked by the next
+    // block) and a column before m (later exits are not needed).  A block
+    // without events gets a start far past every step.
+    const int emax = min(H - 1, n - 1 - r0), xmax = min(H - 2, m - 2 - r0 - b);
+    c.E = emax >= 0 ? c.g * (H + 1) - b : 0x40000000;
+    c.emax = max(emax, 0);
+    c.X = xmax >= 0 ? c.g * (H + 1) + b + 1 : 0x40000000;
+    c.xmax = max(xmax, 0);
 }
 
-// Row events of step s (wave-uniform: one lane per event).  Entry of row
-// qH+h at column qH+h-b, exit after column qH+h+b.  The tests:
-//  * entries stop after row n-1 (s_last): in a pair with at most 64 blocks the
-//    band may be wide, and an entry of a block past n would land on the lane
-//    still holding block q-64;
-//  * exits need q >= 0 (q & 63 of a negative q names a lane with a live block)
-//    and a column before m: an exit past the last column would land on the
-//    lane's next block, whose rows keep their x from then on.
-// Other spurious events are harmless: entries at columns <= 0 find the +inf
-// the block started with; rows past n never feed row n-1.  Exits of a block's
-// last row are not needed: that row leaves the window when the block ends.
-// With 64(H+1) = 2b+H the entry of row qH is the step block q starts on; the
-// block switch comes first.
+// Window events of step s, detected per lane from its own block: the lane
+// whose row h = s - E enters sets that row's left value to +inf, the lane
+// whose row h = s - X leaves sets x_h to kBig.  Consecutive blocks' events lie
+// H+1 steps apart and each block has at most H of each kind, so at most one
+// lane has an entry and one an exit at any step; its row index, read from the
+// first active lane, is wave-uniform and each event is one indexed register
+// move on one lane (the empty asm statements keep each a one-lane branch:
+// without them the compiler turns it into a select of the whole register
+// vector).  A lane takes block g+64 no later than that block's first entry
+// (with 64(H+1) = 2b+H on the same step, the switch first), and exits come
+// before its block ends, so every event finds its block on its lane.
 template <int H>
-__device__ __forceinline__ void cyc_events(int s, RowCounter &en, RowCounter &ex, typename CycVec<H>::T &x,
-                                           typename CycVec<H>::T &O, int lane, int s_last, int m) {
-    // The empty asm statements keep each move a one-lane branch: without them
-    // the compiler turns it into a select of the whole register vector.
-    if (en.h < H && s <= s_last) {
-        if (lane == (en.q & 63)) {
-            asm volatile("");
-            O[en.h] = kInf;
-        }
+__device__ __forceinline__ void cyc_events(int s, const CycLane<H> &c, typename CycVec<H>::T &x,
+                                           typename CycVec<H>::T &O) {
+    const int he = s - c.E;
+    if (static_cast<unsigned>(he) <= static_cast<unsigned>(c.emax)) {
+        asm volatile("");
+        O[__builtin_amdgcn_readfirstlane(he)] = kInf;
     }
-    en.advance<H>();
-    if (ex.h <= H - 2 && ex.q >= 0 && s - ex.q < m) {
-        if (lane == (ex.q & 63)) {
-            asm volatile("");
-            x[ex.h] = kBig;
-        }
+    const int hx = s - c.X;
+    if (static_cast<unsigned>(hx) <= static_cast<unsigned>(c.xmax)) {
+        asm volatile("");
+        x[__builtin_amdgcn_readfirstlane(hx)] = kBig;
     }
-    ex.advance<H>();
 }
 
 // One step.  y0..y3 hold (or are loading) y at this lane's columns of steps
@@ -110,10 +114,9 @@ __device__ __forceinline__ void cyc_events(int s, RowCounter &en, RowCounter &ex
 template <int H>
 __device__ __forceinline__ void cyc_step(int s, CycLane<H> &c, typename CycVec<H>::T &x, typename CycVec<H>::T &O,
                                          typename CycVec<H>::T &N, float &up_in, float &diag_in, float &raw_up,
-                                         float &raw_diag, RowCounter &en, RowCounter &ex, float &y0, float &y1,
+                                         float &raw_diag, float &y0, float &y1,
                                          float &y2, float &y3, const float *__restrict__ xp,
-                                         const float *__restrict__ yp, int lane, int n, int m, int b, int Qf,
-                                         int s_last) {
+                                         const float *__restrict__ yp, int n, int m, int b, int Qf) {
     if (s > c.gend) {  // this lane's block left the window: take block g+64
         c.g += 64;
         cyc_block<H>(c, x, xp, yp, n, m, b, Qf);
@@ -137,7 +140,7 @@ __device__ __forceinline__ void cyc_step(int s, CycLane<H> &c, typename CycVec<H
         up_in = s > c.tphi ? kInf : raw_up;
         diag_in = s - 1 > c.tphi ? kInf : raw_diag;
     }
-    cyc_events<H>(s, en, ex, x, O, lane, s_last, m);
+    cyc_events<H>(s, c, x, O);
     const float yv = y0;
     float diag = diag_in, up = up_in;
 #pragma unroll
@@ -170,7 +173,6 @@ __device__ __forceinline__ void cyc_item(const WaveItem it, const float *__restr
     const float *__restrict__ yp = ws + sc.pstart;
     const int Qf = (n - 1) / H, hf = (n - 1) - Qf * H;
     const int sfinal = (m - 1) + Qf;
-    const int s_last = Qf * (H + 1) + hf - b;  // entry step of row n-1
 
     CycLane<H> c;
     c.g = lane;
@@ -184,9 +186,6 @@ __device__ __forceinline__ void cyc_item(const WaveItem it, const float *__restr
     float up_in = kInf;
     float diag_in = lane == 0 ? 0.0f : kInf;
     float raw_up = kInf, raw_diag = kInf;  // unmasked values received in the last two steps
-    RowCounter en, ex;
-    en.init<H>(b);
-    ex.init<H>(-b - 1);
 
     // Four steps per iteration, so that the y prefetch registers rotate by
     // name instead of by copies.
@@ -196,30 +195,30 @@ __device__ __forceinline__ void cyc_item(const WaveItem it, const float *__restr
     for (; s + 3 <= sfinal; s += 4) {
         q2 = c.yl[s + 2];
         q3 = c.yl[s + 3];
-        cyc_step<H>(s, c, x, A, Bv, up_in, diag_in, raw_up, raw_diag, en, ex, q0, q1, q2, q3, xp, yp, lane, n, m, b,
-                    Qf, s_last);
-        cyc_step<H>(s + 1, c, x, Bv, A, up_in, diag_in, raw_up, raw_diag, en, ex, q1, q2, q3, q0, xp, yp, lane, n,
-                    m, b, Qf, s_last);
+        cyc_step<H>(s, c, x, A, Bv, up_in, diag_in, raw_up, raw_diag, q0, q1, q2, q3, xp, yp, n, m, b,
+                    Qf);
+        cyc_step<H>(s + 1, c, x, Bv, A, up_in, diag_in, raw_up, raw_diag, q1, q2, q3, q0, xp, yp, n, m,
+                    b, Qf);
         q0 = c.yl[s + 4];
         q1 = c.yl[s + 5];
-        cyc_step<H>(s + 2, c, x, A, Bv, up_in, diag_in, raw_up, raw_diag, en, ex, q2, q3, q0, q1, xp, yp, lane, n,
-                    m, b, Qf, s_last);
-        cyc_step<H>(s + 3, c, x, Bv, A, up_in, diag_in, raw_up, raw_diag, en, ex, q3, q0, q1, q2, xp, yp, lane, n,
-                    m, b, Qf, s_last);
+        cyc_step<H>(s + 2, c, x, A, Bv, up_in, diag_in, raw_up, raw_diag, q2, q3, q0, q1, xp, yp, n, m,
+                    b, Qf);
+        cyc_step<H>(s + 3, c, x, Bv, A, up_in, diag_in, raw_up, raw_diag, q3, q0, q1, q2, xp, yp, n, m,
+                    b, Qf);
     }
     const int rem = sfinal + 1 - s;  // 0..3 steps left
     if (rem >= 1) {
         q2 = c.yl[s + 2];
         q3 = c.yl[s + 3];
-        cyc_step<H>(s, c, x, A, Bv, up_in, diag_in, raw_up, raw_diag, en, ex, q0, q1, q2, q3, xp, yp, lane, n, m, b,
-                    Qf, s_last);
+        cyc_step<H>(s, c, x, A, Bv, up_in, diag_in, raw_up, raw_diag, q0, q1, q2, q3, xp, yp, n, m, b,
+                    Qf);
     }
     if (rem >= 2)
-        cyc_step<H>(s + 1, c, x, Bv, A, up_in, diag_in, raw_up, raw_diag, en, ex, q1, q2, q3, q0, xp, yp, lane, n,
-                    m, b, Qf, s_last);
+        cyc_step<H>(s + 1, c, x, Bv, A, up_in, diag_in, raw_up, raw_diag, q1, q2, q3, q0, xp, yp, n, m,
+                    b, Qf);
     if (rem >= 3)
-        cyc_step<H>(s + 2, c, x, A, Bv, up_in, diag_in, raw_up, raw_diag, en, ex, q2, q3, q0, q1, xp, yp, lane, n,
-                    m, b, Qf, s_last);
+        cyc_step<H>(s + 2, c, x, A, Bv, up_in, diag_in, raw_up, raw_diag, q2, q3, q0, q1, xp, yp, n, m,
+                    b, Qf);
     const float res = (rem & 1) ? Bv[hf] : A[hf];
     if (lane == (Qf & 63)) DI.out[it.slot] = res;
 }
