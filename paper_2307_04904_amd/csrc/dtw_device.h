@@ -100,24 +100,5 @@ struct XVec {
     typedef float T __attribute__((ext_vector_type(H < 16 ? 16 : H)));
 };
 
-struct RowCounter {  // t = s + off written as q(H+1) + h with 0 <= h <= H (q < 0 before the first event)
-    int q, h;
-    template <int H>
-    __device__ __forceinline__ void init(int off) {
-        q = off >= 0 ? off / (H + 1) : -((-off + H) / (H + 1));
-        h = off - q * (H + 1);
-    }
-    template <int H>
-    __device__ __forceinline__ void advance() {  // two selects on one compare
-        const bool wrap = h == H;
-        const int h1 = h + 1, q1 = q + 1;
-        h = wrap ? 0 : h1;
-        q = wrap ? q1 : q;
-    }
-    // Lane of the event at this slot, or -1 (no lane) for the empty slot h == H.
-    template <int H>
-    __device__ __forceinline__ int lane() const { return h < H ? q : -1; }
-};
-
 }  // namespace
 }  // namespace dtwmi

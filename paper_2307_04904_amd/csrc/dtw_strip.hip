@@ -84,47 +84,41 @@ __device__ __forceinline__ KahanCell lane_shift_down(KahanCell v, KahanCell fill
     return {lane_shift_down(v.s, fill.s), lane_shift_down(v.c, fill.c)};
 }
 
-// Window edges by row events.  With the skew of this wavefront, a row of the
-// strip enters the window (column r-b) at step l(H+1)+h-be and leaves it
-// (column r+b+1) at step l(H+1)+h+bx+1, where l, h are the wave-local lane and
-// strip row and be, bx are the band shifted by the wavefront's offset: at most
-// one row enters and one row leaves per step, and the lane and strip row of
-// each event are wave-uniform.  A row outside the window has its x replaced
-// by 1e30 (its local cost overflows), so the cell loop itself carries no test.
+// Window edges by row events.  With the skew of this wavefront, row h of
+// lane l (strip rows rbase..rbase+H-1, column s - skew at step s) enters the
+// window (column r-b) at step E + h and leaves it (column r+b+1) at step X + h,
+// E = rbase + skew - b, X = rbase + skew + b + 1.  Consecutive lanes' events
+// lie H+1 steps apart and each lane has H of each kind, so at most one lane of
+// a wavefront enters and one leaves per step; each lane detects its own
+// events, and the row index, read from the single active lane, is
+// wave-uniform.  A row outside the window has its x replaced by 1e30 (its
+// local cost overflows), so the cell loop itself carries no test.  Entries at
+// columns <= 0 repeat the start-up value; events of rows past n touch cells
+// that never feed row n-1.  Each move is a one-lane branch; the empty asm
+// statement keeps the compiler from turning it into a select of the whole
+// register vector.
 struct BandEvents {
-    RowCounter en, ex;
-    int col_shift;  // column of lane l at step s = s - l - col_shift
+    int E, X;
 
-    template <int H>
-    __device__ __forceinline__ void init(int band, int n_rows, int wave, int D) {
-        const int row0 = wave * 64 * H;
-        (void)n_rows;
-        col_shift = wave * (64 + D);
-        const int shift = row0 + col_shift;
-        en.init<H>(band - shift);       // entry at step s: s + b - shift = l(H+1) + h
-        ex.init<H>(-band - shift - 1);  // exit at step s:  s - b - shift - 1 = l(H+1) + h
+    __device__ __forceinline__ void init(int rbase, int skew, int band) {
+        E = rbase + skew - band;
+        X = rbase + skew + band + 1;
     }
 
-    // Apply the events of step s (counters are at step s on entry), then advance.
-    // Only the slot h == H (no row) needs a test, folded into the lane
-    // compare (it names lane -1).  An event whose lane q is outside 0..63
-    // matches no lane; entries at columns <= 0 repeat the
-    // start-up value; events of rows past n touch cells that never feed row
-    // n-1.  Each move is a one-lane branch; the empty asm statement keeps the
-    // compiler from turning it into a select of the whole register vector.
     template <int H>
     __device__ __forceinline__ void step(int s, typename XVec<H>::T &xe, const typename XVec<H>::T &xr, int lane) {
-        (void)s;
-        if (lane == en.lane<H>()) {
+        (void)lane;
+        const int he = s - E;
+        if (static_cast<unsigned>(he) < static_cast<unsigned>(H)) {
             asm volatile("");
-            xe[en.h] = xr[en.h];
+            const int h = __builtin_amdgcn_readfirstlane(he);
+            xe[h] = xr[h];
         }
-        en.advance<H>();
-        if (lane == ex.lane<H>()) {
+        const int hx = s - X;
+        if (static_cast<unsigned>(hx) < static_cast<unsigned>(H)) {
             asm volatile("");
-            xe[ex.h] = kBig;
+            xe[__builtin_amdgcn_readfirstlane(hx)] = kBig;
         }
-        ex.advance<H>();
     }
 };
 
@@ -196,7 +190,7 @@ __device__ __forceinline__ void strip_item(const WaveItem it, const float *__res
         Bv[h] = ACC::inf();
     }
     BandEvents ev;
-    if constexpr (EVENTS) ev.init<H>(band, n, wave, D);
+    if constexpr (EVENTS) ev.init(rbase, skew, band);
     if constexpr (G > 1) {
         for (int k = threadIdx.x; k < (G - 1) * kRing; k += 64 * G) ring[k / kRing][k % kRing] = ACC::inf();
         __syncthreads();
