@@ -151,9 +151,9 @@ __device__ __forceinline__ void cyc_step(int s, CycLane<H> &c, typename CycVec<H
         up = v;
         N[h] = v;
     }
-    // DPP wave_ror:1: lane l receives lane l-1, lane 0 receives lane 63
-    const float recv = __int_as_float(
-        __builtin_amdgcn_update_dpp(__float_as_int(kInf), __float_as_int(N[H - 1]), 0x13C, 0xF, 0xF, false));
+    // DPP wave_ror:1: lane l receives lane l-1, lane 0 receives lane 63 (every
+    // lane has a source, so no old value is needed)
+    const float recv = __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(N[H - 1]), 0x13C, 0xF, 0xF, true));
     raw_diag = raw_up;
     raw_up = recv;
     diag_in = up_in;

@@ -298,6 +298,11 @@ def test_cyclic_kernel_each_block_height(H):
         synth.small_random(seed=400 + H, N=8, len_lo=lo + 1, len_hi=lo + bmax // 3, window=bmax // 3),
         # at most 64 blocks: any band width, lengths from 2 points up
         synth.small_random(seed=500 + H, N=12, len_lo=2, len_hi=64 * H, window=3 * H + 1),
+        # two lane cycles with |n-m| near the band limit: windows clipped at
+        # the last column on lanes that still take another block
+        synth.pack([synth.random_walk(rng, L) for L in
+                    (128 * H, 128 * H - bmax + 4, 128 * H - 2, 128 * H - bmax + 2, 128 * H - 1, 128 * H - bmax + 1)],
+                   "clip%d" % H, bmax),
     ]
     for k, ds in enumerate(cases):
         got, info = _run_plan(ds, kernel="cyclic", rows_per_lane=H)
