@@ -224,6 +224,8 @@ def main(argv=None):
                     help="storage type of the series (the long-series workload's precision study)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target duration of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--describe", metavar="FILE", default="",
+                    help="write the plan's kernel groups (dtw_plan_describe JSON) to FILE")
     ap.add_argument("--copy-calibration-mb", type=float, default=0.0,
                     help="only run 5 device-to-device copies of this many MiB (reference for HBM byte counters)")
     args = ap.parse_args(argv)
@@ -266,6 +268,9 @@ def main(argv=None):
     plan_s = time.perf_counter() - t_plan
     info = plan.info()
     plan_desc = plan.describe()
+    if args.describe:
+        with open(args.describe, "w") as f:
+            json.dump(plan_desc, f)
     stream = torch.cuda.current_stream(dev)
 
     for _ in range(args.warmup):

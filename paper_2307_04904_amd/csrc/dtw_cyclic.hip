@@ -32,6 +32,7 @@ namespace {
 //  * replaces a received boundary value by +inf past the previous block's
 //    window (its last row exits there; its lane may already work on another
 //    block).
+
 // Register vector of a block's H rows (x, and the two column buffers), with a
 // wave-uniform runtime index turned into one indexed register move
 // (s_set_gpr_idx): the compiler does that for vectors of more than 8 elements
