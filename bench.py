@@ -231,8 +231,8 @@ def main(argv=None):
     args = ap.parse_args(argv)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build measures one GPU only (the all-pairs matrix shards by pair ranges with no "
-              "exchange; see DESIGN.md). Run with --gpus 1.", file=sys.stderr)
+        print("bench.py: measures one GPU only (the all-pairs matrix shards by pair ranges with no exchange "
+              "between GPUs, so one GPU's share is the measured unit). Run with --gpus 1.", file=sys.stderr)
         return 2
 
     import torch
