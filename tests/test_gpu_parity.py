@@ -160,6 +160,10 @@ def test_series_longer_than_one_wavefront(accum):
             # relative error bound (k-1)*2^-24); the compensated sums keep 1e-5
             assert_close(got, ref, tol=REL_TOL_LONG_PLAIN if accum == "plain" else REL_TOL,
                          what="long %s w=%d" % (accum, w))
+        if accum == "plain":
+            # windowed pairs go to the cyclic kernel by default; the multi-wavefront
+            # strips (window events per lane, boundary rows through LDS) must agree bit for bit
+            assert np.array_equal(run(ds, kernel="wave"), got), "long w=%d: strips differ" % w
 
 
 @pytest.mark.parametrize("accum", ["kahan", "fp64"])
