@@ -106,8 +106,7 @@ struct BandEvents {
     }
 
     template <int H>
-    __device__ __forceinline__ void step(int s, typename XVec<H>::T &xe, const typename XVec<H>::T &xr, int lane) {
-        (void)lane;
+    __device__ __forceinline__ void step(int s, typename XVec<H>::T &xe, const typename XVec<H>::T &xr) {
         const int he = s - E;
         if (static_cast<unsigned>(he) < static_cast<unsigned>(H)) {
             asm volatile("");
@@ -224,7 +223,7 @@ __device__ __forceinline__ void strip_item(const WaveItem it, const float *__res
     int s = 0;
     for (; s + 2 <= sfinal + 1; s += 2) {
         const float y2 = yat(s + 2), y3 = yat(s + 3);
-        if constexpr (EVENTS) ev.step<H>(s, x, xr, lane);
+        if constexpr (EVENTS) ev.step<H>(s, x, xr);
         strip_step<ACC, H, PERCELL>(s - skew, y0, x, A, Bv, up_in, diag_in, rbase, band);
         {
             const T recv = lane_shift_down(Bv[H - 1], boundary(s + 1));
@@ -232,7 +231,7 @@ __device__ __forceinline__ void strip_item(const WaveItem it, const float *__res
             diag_in = up_in;
             up_in = recv;
         }
-        if constexpr (EVENTS) ev.step<H>(s + 1, x, xr, lane);
+        if constexpr (EVENTS) ev.step<H>(s + 1, x, xr);
         strip_step<ACC, H, PERCELL>(s + 1 - skew, y1, x, Bv, A, up_in, diag_in, rbase, band);
         {
             const T recv = lane_shift_down(A[H - 1], boundary(s + 2));
@@ -248,7 +247,7 @@ __device__ __forceinline__ void strip_item(const WaveItem it, const float *__res
     }
     T res;
     if (s <= sfinal) {  // one step left (s == sfinal)
-        if constexpr (EVENTS) ev.step<H>(s, x, xr, lane);
+        if constexpr (EVENTS) ev.step<H>(s, x, xr);
         strip_step<ACC, H, PERCELL>(s - skew, y0, x, A, Bv, up_in, diag_in, rbase, band);
         res = pick<H>(Bv, hf);
     } else {
