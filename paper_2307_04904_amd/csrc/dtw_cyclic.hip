@@ -115,9 +115,9 @@ __device__ __forceinline__ void cyc_events(int s, const CycLane<H> &c, typename 
 template <int H>
 __device__ __forceinline__ void cyc_step(int s, CycLane<H> &c, typename CycVec<H>::T &x, typename CycVec<H>::T &O,
                                          typename CycVec<H>::T &N, float &up_in, float &diag_in, float &raw_up,
-                                         float &raw_diag, float &y0, float &y1,
-                                         float &y2, float &y3, const float *__restrict__ xp,
-                                         const float *__restrict__ yp, int n, int m, int b, int Qf) {
+                                         float &raw_diag, float &y0, float &y1, float &y2, float &y3,
+                                         const float *__restrict__ xp, const float *__restrict__ yp, int n, int m,
+                                         int b, int Qf) {
     if (s > c.gend) {  // this lane's block left the window: take block g+64
         c.g += 64;
         cyc_block<H>(c, x, xp, yp, n, m, b, Qf);
