@@ -224,8 +224,13 @@ __device__ __forceinline__ void cyc_item(const WaveItem it, const float *__restr
     if (lane == (Qf & 63)) DI.out[it.slot] = res;
 }
 
+// Waves per SIMD the register allocation aims for: H = 28 fits 4 (126 VGPRs,
+// no scratch) instead of 3 when asked; H = 20, 24 and 32 would spill.
 template <int H>
-__global__ __launch_bounds__(64) void k_strip_cyc(const float *__restrict__ ws, const SeriesInfo *__restrict__ ser,
+constexpr int cyc_min_waves() { return H == 28 ? 4 : 1; }
+
+template <int H>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(cyc_min_waves<H>()))) void k_strip_cyc(const float *__restrict__ ws, const SeriesInfo *__restrict__ ser,
                                                   const DatasetInfo *__restrict__ dsi,
                                                   const WaveItem *__restrict__ items, unsigned *__restrict__ queue,
                                                   unsigned n_items) {
