@@ -205,8 +205,10 @@ def quantisation_error(dsets, dsets_f32, gpu_outs, n_pairs=64):
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=200,
+                    help="timed steps; the first launches after the synchronisation wait ~1.8 ms in all for "
+                         "the GPU to pick up work, which 20 steps of c2 would count as 6%% of the time")
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--kernel", default="auto", choices=["auto", "lane", "wave", "cyclic"])
     ap.add_argument("--accum", default="plain", choices=["plain", "kahan", "fp64"])
