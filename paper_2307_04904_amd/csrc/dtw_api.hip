@@ -111,33 +111,38 @@ struct WaveGroup {
 };
 
 
-// Cost model shared by both wavefront families: wavefront-steps times VALU
-// instructions per step (3 per cell row plus loop overhead per step, from the
-// instruction mix of the compiled loops), times a measured factor per kernel
-// instance: the median time per modelled instruction that DTW_FLAG_AUTOTUNE
-// found for that instance over the buckets of the 64-dataset batched workload
-// on MI355X, relative to the unwindowed 12-row strip; the cyclic column was
-// then scaled by the factor (0.5) that gave the fastest plan of that workload
-// with the per-lane window events of the cyclic kernel.  The factors carry
-// what the instruction count misses: scalar work and waits of the window
-// events (windowed strips, cyclic kernel) and the occupancy of each register
-// budget.
+// Cost model of the wavefront families, in VALU instructions of one
+// wavefront.  Strips: wavefront-steps times instructions per step (3 per cell
+// row plus loop overhead per step, from the instruction mix of the compiled
+// loops), times a measured factor per instance: the median time per modelled
+// instruction that DTW_FLAG_AUTOTUNE found for that instance over the buckets
+// of the 64-dataset batched workload on MI355X, relative to the unwindowed
+// 12-row strip (the factors carry the scalar work and waits of the window
+// events and the occupancy of each register budget).  Cyclic kernel: the
+// instruction count of its compiled loop (3 per cell row plus 13 per step:
+// y address, block-switch test, the two window-event tests and moves, the
+// boundary rotation and its mask) and ~45 per block switch, at the strips'
+// issue rate: with its window events detected per lane the cyclic kernel
+// issues VALU as fast as a strip (0.43-0.48 per wave-cycle at 20-32 rows).
+// On the batched workload this plain count chose better than the calibrated
+// factors (11,150 against 11,070 GCUPS on one box; 1.15x the count 11,145,
+// 1.3x 10,920).
 constexpr int kMaxQueues = 128;  // queue counters of a plan (one per wavefront kernel group)
 constexpr int64_t kStripStepOverhead = 15;
-constexpr int64_t kCyclicStepOverhead = 20;
+constexpr int64_t kCyclicStepOverhead = 13;
+constexpr int64_t kCyclicSwitchCost = 45;
 
 struct CalEntry {
     int H;
-    int strip_plain, strip_banded, cyclic;  // x100
+    int strip_plain, strip_banded;  // x100
 };
-const CalEntry kCal[] = {{1, 100, 300, 172},  {2, 100, 304, 170},  {4, 87, 236, 145},  {8, 95, 197, 120},
-                         {12, 103, 150, 107}, {16, 108, 151, 106}, {24, 112, 163, 116}, {32, 118, 171, 114},
-                         {48, 125, 180, 115}, {64, 130, 190, 115}};
+const CalEntry kCal[] = {{1, 100, 300},  {2, 100, 304},  {4, 87, 236},   {8, 95, 197},   {12, 103, 150},
+                         {16, 108, 151}, {24, 112, 163}, {32, 118, 171}, {48, 125, 180}, {64, 130, 190}};
 
-int64_t cal_factor(int H, int which) {  // which: 0 plain strip, 1 windowed strip, 2 cyclic
+int64_t cal_factor(int H, bool banded) {
     for (const CalEntry &c : kCal)
-        if (c.H >= H) return which == 0 ? c.strip_plain : which == 1 ? c.strip_banded : c.cyclic;
-    return which == 0 ? 130 : which == 1 ? 190 : 115;
+        if (c.H >= H) return banded ? c.strip_banded : c.strip_plain;
+    return banded ? 190 : 130;
 }
 
 // Steps a strip workgroup takes on an n x m pair (n = rows spread over lanes).
@@ -151,7 +156,7 @@ int64_t strip_steps(StripShape sh, int64_t n, int64_t m) {
 constexpr int64_t kMultiWaveFactor = 120;
 
 int64_t strip_cost(StripShape sh, int64_t n, int64_t m, bool banded) {
-    const int64_t c = sh.G * strip_steps(sh, n, m) * (3 * sh.H + kStripStepOverhead) * cal_factor(sh.H, banded ? 1 : 0) / 100;
+    const int64_t c = sh.G * strip_steps(sh, n, m) * (3 * sh.H + kStripStepOverhead) * cal_factor(sh.H, banded) / 100;
     return sh.G > 1 ? c * kMultiWaveFactor / 100 : c;
 }
 
@@ -167,7 +172,9 @@ bool cyclic_fits(int H, int64_t n, int64_t b) {
 int64_t cyclic_steps(int H, int64_t n, int64_t m) { return m + (n - 1) / H; }
 
 int64_t cyclic_cost(int H, int64_t n, int64_t m) {
-    return cyclic_steps(H, n, m) * (3 * H + kCyclicStepOverhead) * cal_factor(H, 2) / 100;
+    const int64_t blocks = (n + H - 1) / H;
+    const int64_t switches = blocks > 64 ? blocks - 64 : 0;
+    return cyclic_steps(H, n, m) * (3 * H + kCyclicStepOverhead) + switches * kCyclicSwitchCost;
 }
 
 // Strip shape for a pair whose shorter series has n points: of the two
