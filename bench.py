@@ -8,7 +8,12 @@ cell updates per second over the admissible (in-window) cells of every pair.
 
 Printed: one JSON line with the value, the roofline of the dominant DP kernel
 (FP32 VALU bound, 3 VALU lane-operations per cell: sub, min3, fma), and the
-FP64 CPU oracle timed on a bounded sample of the same workload.
+FP64 CPU oracle timed on a bounded sample of the same workload.  The default
+run (8000 series of 256 points, window 25, the largest single-matrix
+workload) adds, under "extra": the equal-length banded matrix (1000 x 512,
+window 51) as the equal-size rate, the 64-dataset batched plan replayed from a
+HIP graph with its ratio to that rate, and the 500 x 4096 long-series matrix
+under the default accumulation with its error against the oracle.
 """
 from __future__ import annotations
 
@@ -38,11 +43,19 @@ OPS_PER_CELL = 3
 #   fp64:  sub, mul, min, min, add in FP64 (5), against the FP64 vector peak
 #          78.6 TFLOP/s = 39.32 T lane-ops/s (an FMA counted as one op)
 PEAK_FP64_LANE_OPS_T = 78.6 / 2
+#   auto, rebased: the plain cell (the rebased form adds per lane a subtract per
+#          received value and a renormalisation every 16-32 steps, ~1-3%, not
+#          counted as algorithmic work)
 MODE_OPS = {"plain": (3, PEAK_LANE_OPS_T, "TOP/s (FP32 VALU lane-ops)"),
+            "auto": (3, PEAK_LANE_OPS_T, "TOP/s (FP32 VALU lane-ops)"),
+            "rebased": (3, PEAK_LANE_OPS_T, "TOP/s (FP32 VALU lane-ops)"),
             "kahan": (11, PEAK_LANE_OPS_T, "TOP/s (FP32 VALU lane-ops)"),
             "fp64": (5, PEAK_FP64_LANE_OPS_T, "TOP/s (FP64 VALU lane-ops)")}
 # profile summary (profiles/<label>*.md) holding the counter-based HBM traffic of a workload's DP kernel
-PROFILE_LABELS = {("c2", "auto", "plain", "f32"): "lane_band_W103_c2"}
+PROFILE_LABELS = {("c2", "auto", "auto", "f32"): "lane_band_W103_c2",
+                  ("c5", "auto", "auto", "f32"): "lane_band_W51_c5",
+                  ("c3", "auto", "auto", "f32"): "strip_rebased_H64_c3",
+                  ("c4", "auto", "auto", "f32"): "batched_c4"}
 
 WORKLOADS = {
     "c2": "equal-length banded matrix: 1000 random walks x 512, window 51",
@@ -202,6 +215,93 @@ def quantisation_error(dsets, dsets_f32, gpu_outs, n_pairs=64):
     return {"pairs": int(len(a)), "max_rel_err": float(rel.max()), "mean_rel_err": float(rel.mean())}
 
 
+def make_step(plan, stream, use_graph):
+    """One step: an eager plan execute, or the replay of a HIP graph captured from one."""
+    if not use_graph:
+        return (lambda: plan.execute(stream)), None
+    import torch
+    plan.execute(stream)  # the first launches load the code objects outside the capture
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()  # capture needs a stream other than the default one
+    side.wait_stream(stream)
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(g, stream=side):
+            plan.execute(side)
+    torch.cuda.synchronize()
+    return g.replay, g
+
+
+def time_steps(step, stream, steps, warmup):
+    """(ms per step, wall seconds) over `steps` steps after `warmup`, by events on `stream`."""
+    import torch
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    with torch.cuda.stream(stream):
+        ev0.record(stream)
+        for _ in range(steps):
+            step()
+        ev1.record(stream)
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1) / steps, time.perf_counter() - t0
+
+
+def extra_workloads(dev, stream, steps):
+    """Rates of the other workloads in the same run (see the module docstring)."""
+    import oracle
+    import torch
+    from paper_2307_04904_amd import binding, synth
+    out = {}
+
+    def rate(dsets, graph, n_steps, accum="auto"):
+        series = [binding.device_series(ds, dev) for ds in dsets]
+        outs = [torch.full((max(1, ds.n_pairs),), float("nan"), device=dev) for ds in dsets]
+        plan = binding.Plan([(s_, ds.lengths, ds.offsets, ds.window, o) for s_, ds, o in zip(series, dsets, outs)],
+                            dtype=dsets[0].dtype, accum=accum, timing=True)
+        step, g = make_step(plan, stream, graph)
+        ms, _ = time_steps(step, stream, n_steps, max(3, n_steps // 10))
+        cells = plan.info()["band_cells"]
+        kms = []
+        for _ in range(5):
+            plan.execute(stream)
+            kms.append(plan.last_kernel_ms())
+        desc = plan.describe()
+        del g
+        plan.destroy()
+        res = {"gcups": round(cells / (ms * 1e-3) / 1e9, 1), "ms_per_step": round(ms, 4),
+               "kernel_ms": round(statistics.mean(kms), 4), "band_cells": cells,
+               "kernels": sorted({"%s/%s" % (g_["kernel"], g_["accum"]) for g_ in desc["wave_groups"]} |
+                                 {"lane:%d/%s" % (g_["W"], g_["accum"]) for g_ in desc["lane_groups"]})}
+        return res, [o.cpu().numpy() for o in outs]
+
+    c2, _ = rate([synth.config2()], False, max(50, steps // 2))
+    out["c2_1000x512_w51"] = dict(c2, description=WORKLOADS["c2"])
+    c4, c4_outs = rate(synth.config4(), True, 20)
+    c4["ratio_to_equal_size_rate"] = round(c4["gcups"] / c2["gcups"], 4)
+    out["c4_batched_64_datasets"] = dict(c4, description=WORKLOADS["c4"], timing="hip graph replays")
+    ds3 = synth.config3()
+    c3, c3_out = rate([ds3], False, 10)
+    pi, pj = [], []
+    rng = np.random.default_rng(4096)
+    while len(pi) < 300:
+        i, j = sorted(rng.integers(0, ds3.N, size=2))
+        if i != j:
+            pi.append(i)
+            pj.append(j)
+    pi, pj = np.array(pi, dtype=np.int32), np.array(pj, dtype=np.int32)
+    ref, _ = oracle.dtw_pairs(synth.stored_as_f64(ds3), ds3.offsets, ds3.lengths, pi, pj, ds3.window)
+    k = pi.astype(np.int64) * ds3.N - pi.astype(np.int64) * (pi + 1) // 2 + (pj - pi - 1)
+    rel = np.abs(c3_out[0][k].astype(np.float64) - ref) / ref
+    c3.update(accum="auto (rebased FP32 sums on these 8,191-cell paths)", pairs_checked=len(pi),
+              max_rel_err=float(rel.max()), mean_rel_err=float(rel.mean()), description=WORKLOADS["c3"])
+    out["c3_500x4096_default_accumulation"] = c3
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -209,9 +309,9 @@ def main(argv=None):
                     help="timed steps; the first launches after the synchronisation wait ~1.8 ms in all for "
                          "the GPU to pick up work, which 20 steps of c2 would count as 6%% of the time")
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="c5", choices=sorted(WORKLOADS))
     ap.add_argument("--kernel", default="auto", choices=["auto", "lane", "wave", "cyclic"])
-    ap.add_argument("--accum", default="plain", choices=["plain", "kahan", "fp64"])
+    ap.add_argument("--accum", default="auto", choices=["auto", "plain", "rebased", "kahan", "fp64"])
     ap.add_argument("--rows-per-lane", type=int, default=0,
                     help="force the strip / cyclic rows per lane (0 = cost model)")
     ap.add_argument("--silhouette", type=int, default=0, metavar="K",
@@ -228,6 +328,10 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--describe", metavar="FILE", default="",
                     help="write the plan's kernel groups (dtw_plan_describe JSON) to FILE")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the extra workloads of the default run (equal-size, batched graph, long series)")
+    ap.add_argument("--graph", action="store_true",
+                    help="time replays of a HIP graph captured from one execute instead of eager executes")
     ap.add_argument("--copy-calibration-mb", type=float, default=0.0,
                     help="only run 5 device-to-device copies of this many MiB (reference for HBM byte counters)")
     args = ap.parse_args(argv)
@@ -275,19 +379,8 @@ def main(argv=None):
             json.dump(plan_desc, f)
     stream = torch.cuda.current_stream(dev)
 
-    for _ in range(args.warmup):
-        plan.execute(stream)
-    torch.cuda.synchronize(dev)
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    for _ in range(args.steps):
-        plan.execute(stream)
-    ev1.record(stream)
-    torch.cuda.synchronize(dev)
-    wall = time.perf_counter() - t0
-    ms_per_step = ev0.elapsed_time(ev1) / args.steps
+    step, graph = make_step(plan, stream, args.graph)
+    ms_per_step, wall = time_steps(step, stream, args.steps, args.warmup)
 
     # DP-kernel-only durations (HIP events recorded by the library on the same stream)
     kms = []
@@ -313,6 +406,7 @@ def main(argv=None):
         "vs_baseline": None,
         "dtype": "f64" if args.accum == "fp64" else "f32",
         "data": "synthetic",
+        "timing": "hip graph replays" if args.graph else "eager executes",
         "config": {"workload": (dsets[0].name + ("_medoids%d" % MEDOIDS if pair_list is not None else "")
                                 if len(dsets) == 1 else args.workload + "_batched_64_datasets"),
                    "description": WORKLOADS[args.workload], "datasets": len(dsets),
@@ -322,8 +416,8 @@ def main(argv=None):
                    "pairs": info["pairs"], "band_cells": cells, "swept_cells": info["computed_cells"],
                    "kernel": args.kernel, "accum": args.accum, "storage": dsets[0].dtype,
                    "dispatch": args.dispatch, "autotune": args.autotune, "rows_per_lane": args.rows_per_lane,
-                   "kernels": [g["kernel"] for g in plan_desc["wave_groups"]] + ["lane:%d" % g["W"] for g in
-                                                                               plan_desc["lane_groups"]],
+                   "kernels": ["%s/%s" % (g["kernel"], g["accum"]) for g in plan_desc["wave_groups"]] +
+                              ["lane:%d/%s" % (g["W"], g["accum"]) for g in plan_desc["lane_groups"]],
                    "plan_create_s": round(plan_s, 3), "tuned_buckets": info["n_tuned_buckets"],
                    "tuned_changed": info["n_tuned_changed"]},
         "pct_peak_cell_rate": round(100.0 * value / (PEAK_LANE_OPS_T * 1e3 / OPS_PER_CELL), 2),
@@ -375,7 +469,11 @@ def main(argv=None):
         if dsets[0].dtype != "f32" and len(dsets) == 1:
             line["gpu_vs_oracle_on_fp32_source"] = quantisation_error(
                 dsets, make_datasets(args.workload, "f32"), [o.cpu().numpy() for o in outs])
+    del graph  # the captured graph refers to the plan's workspace
     plan.destroy()
+    if args.workload == "c5" and not args.no_extra and pair_list is None and args.accum == "auto" \
+            and args.kernel == "auto" and args.dtype == "f32":
+        line["extra"] = extra_workloads(dev, stream, args.steps)
     print(json.dumps(line), flush=True)
     return 0
 

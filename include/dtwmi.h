@@ -26,8 +26,8 @@
  *   - Series values must be finite; results for NaN or inf inputs are
  *     unspecified.  The output is always FP32.
  *   - Series may have any length >= 1.  The shorter series of a pair may have
- *     up to 32768 points with PLAIN accumulation and up to 16384 with KAHAN
- *     or FP64; longer returns DTW_ERR_UNSUPPORTED.
+ *     up to 32768 points with AUTO, PLAIN or REBASED accumulation and up to
+ *     16384 with KAHAN or FP64; longer returns DTW_ERR_UNSUPPORTED.
  */
 #ifndef DTWMI_H
 #define DTWMI_H
@@ -49,24 +49,42 @@ typedef enum {
 /* Storage type of the input series (all accumulate in FP32 or FP64). */
 typedef enum { DTW_F32 = 0, DTW_BF16 = 1, DTW_F16 = 2 } dtw_dtype;
 
-/* Accumulation of the cumulative cost:
- *   PLAIN: FP32 sub, min, fused multiply-add per cell.
- *   KAHAN: FP32 with a compensation term carried per cell and a compensated
- *          add of every local cost (the min compares the running sums).
- *   FP64:  the whole recurrence in FP64, the final cost rounded once to FP32. */
-typedef enum { DTW_ACC_PLAIN = 0, DTW_ACC_KAHAN = 1, DTW_ACC_FP64 = 2 } dtw_accum;
+/* Accumulation of the cumulative cost.  The paper fixes no precision; the
+ * accuracy target here is a relative error of at most 1e-5 against an exact
+ * (FP64) evaluation of Eq. (c) for FP32 inputs.
+ *   AUTO:    (the default, 0) per pair: PLAIN when the longest warping path,
+ *            n+m-1 cells, has at most 2048 cells, REBASED otherwise.
+ *   PLAIN:   FP32 sub, min, fused multiply-add per cell.  Each add rounds
+ *            relative to the whole cumulative cost, so the error grows with
+ *            the path length: within 1e-5 up to paths of 2048 cells, about
+ *            1e-5 at 8191 (4096-point series), within 1e-4 beyond.
+ *   KAHAN:   FP32 with a compensation term carried per cell and a compensated
+ *            add of every local cost (the min compares the running sums).
+ *   FP64:    the whole recurrence in FP64, the final cost rounded once to FP32.
+ *   REBASED: the PLAIN cell, but every lane of a kernel keeps its values
+ *            relative to a running base of its own and renormalises them
+ *            every few steps, so each add rounds relative to the small stored
+ *            values; about the accuracy of KAHAN (~1e-6 at 8191-cell paths) at
+ *            a few per cent above the cost of PLAIN. */
+typedef enum {
+    DTW_ACC_AUTO = 0,
+    DTW_ACC_PLAIN = 1,
+    DTW_ACC_KAHAN = 2,
+    DTW_ACC_FP64 = 3,
+    DTW_ACC_REBASED = 4
+} dtw_accum;
 
 /* Kernel family; AUTO picks per dataset and per pair.  The others exist for
  * tests and benchmarks.
  *   LANE:   one pair per lane, the band row kept in registers (all series of
- *           the dataset of equal length, 2*w+1 <= 127, PLAIN only).
+ *           the dataset of equal length, 2*w+1 <= 127; AUTO, PLAIN or REBASED).
  *   WAVE:   one pair per workgroup of 1..16 wavefronts sweeping anti-diagonals,
  *           each lane owning a strip of rows (any lengths, any window, any
  *           accumulation).
  *   CYCLIC: one pair per wavefront; blocks of rows of the longer series cycle
  *           over the 64 lanes and each block only visits the columns its window
- *           admits (PLAIN only).  Pairs without a window, or whose window is too
- *           wide for any instantiated block height, use WAVE. */
+ *           admits (AUTO, PLAIN or REBASED).  Pairs without a window, or whose
+ *           window is too wide for any instantiated block height, use WAVE. */
 typedef enum { DTW_KERNEL_AUTO = 0, DTW_KERNEL_LANE = 1, DTW_KERNEL_WAVE = 2, DTW_KERNEL_CYCLIC = 3 } dtw_kernel;
 
 /* One dataset: N series concatenated in one device buffer. */
@@ -79,15 +97,26 @@ typedef struct dtw_dataset {
     float *out_condensed;   /* device: N*(N-1)/2 floats, written in condensed order */
 } dtw_dataset;
 
+/* Options; a zero-initialised struct means FP32 storage, AUTO accumulation,
+ * AUTO kernel, no flags, the default stream and every pair. */
 typedef struct dtw_options {
     int32_t dtype;  /* dtw_dtype */
-    int32_t accum;  /* dtw_accum */
+    int32_t accum;  /* dtw_accum (0 = AUTO) */
     int32_t kernel; /* dtw_kernel (0 = AUTO) */
     int32_t flags;  /* DTW_FLAG_* bits: TIMING (plan API only), NO_QUEUE, AUTOTUNE */
     int32_t rows_per_lane; /* 0 = automatic.  Else the rows each lane holds in the WAVE and
                               CYCLIC kernels (1..64); a value with no instantiated kernel for a
                               pair returns DTW_ERR_UNSUPPORTED.  Ignored by LANE. */
-    void *stream;   /* hipStream_t used by dtw_pairwise_ex; NULL = default stream */
+    void *stream;   /* hipStream_t used by dtw_pairwise_ex and dtw_pairs; NULL = default stream */
+    /* Output sub-range: only the entries k with k_begin <= k < k_end of every
+     * dataset's output are evaluated and written (the condensed index k(i,j)
+     * for all-pairs plans, the list position for pair lists); the other
+     * entries are left untouched.  k_end <= 0 means the end of the output;
+     * 0, 0 is every pair.  k_begin < 0, or 0 < k_end < k_begin, is
+     * DTW_ERR_INVALID_ARG; a range past a dataset's output is clipped to it.
+     * Splitting [0, N(N-1)/2) into ranges splits the work of a matrix into
+     * independent parts (one per device or per call) with no exchange. */
+    int64_t k_begin, k_end;
 } dtw_options;
 
 #define DTW_FLAG_TIMING 1
@@ -122,14 +151,27 @@ typedef struct dtw_plan_stats {
 } dtw_plan_stats;
 
 /*
- * Short form: FP32 input, PLAIN accumulation, default stream, automatic kernel.
+ * Short form: FP32 input, AUTO accumulation, default stream, automatic kernel.
  * series: device; lengths, offsets: host; out_condensed: device.
- * Blocks until the result is written (it builds and frees a plan internally).
+ * Enqueues the evaluation on the default stream and returns; the result is
+ * valid after that stream is synchronised.  The short forms (this one,
+ * dtw_pairwise_ex, dtw_pairs) keep the plans they build in a cache of the
+ * library, keyed by device, stream, options and the dataset's shape (N,
+ * window, lengths, offsets, and the pair list for dtw_pairs), not by the
+ * buffers: a call whose key is cached re-points the plan at its own series
+ * and output buffers with one small kernel and launches it, without any
+ * allocation, upload or synchronisation.  A call whose key is new builds a
+ * plan (device allocation and upload of its tables, which block the host)
+ * first.  The cache holds up to 8 plans per process; replacing the least
+ * recently used one waits for that plan's last launch to finish.  Calls that
+ * share a key must be made from one host thread at a time (the cache itself is
+ * thread-safe).
  */
 int dtw_pairwise(const float *series, const int32_t *lengths, const int64_t *offsets,
                  int32_t N, int32_t window, float *out_condensed);
 
-/* One dataset with explicit options; blocks until the result is written. */
+/* One dataset with explicit options (NULL = all zero), enqueued on opt->stream
+ * like dtw_pairwise.  DTW_FLAG_TIMING is ignored (it needs the plan API). */
 int dtw_pairwise_ex(const dtw_dataset *ds, const dtw_options *opt);
 
 /*
@@ -193,7 +235,8 @@ typedef struct dtw_pair {
 int dtw_plan_create_pairs(dtw_plan *plan, const dtw_dataset *ds, const dtw_pair *pairs, int64_t n_pairs,
                           float *out, const dtw_options *opt);
 
-/* Blocking form of a pair-list plan: create, execute on opt->stream, synchronise, destroy. */
+/* Short form of a pair-list plan, enqueued on opt->stream with the plan cache
+ * of dtw_pairwise (the list is part of the key; series and out are not). */
 int dtw_pairs(const dtw_dataset *ds, const dtw_pair *pairs, int64_t n_pairs, float *out, const dtw_options *opt);
 
 /*

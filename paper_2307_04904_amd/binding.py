@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_build", "l
 
 DTW_OK, DTW_ERR_INVALID_ARG, DTW_ERR_UNSUPPORTED, DTW_ERR_OUT_OF_MEMORY, DTW_ERR_HIP = range(5)
 DTYPES = {"f32": 0, "bf16": 1, "f16": 2}
-ACCUM = {"plain": 0, "kahan": 1, "fp64": 2}
+ACCUM = {"auto": 0, "plain": 1, "kahan": 2, "fp64": 3, "rebased": 4}
 KERNELS = {"auto": 0, "lane": 1, "wave": 2, "cyclic": 3}
 DTW_FLAG_TIMING = 1
 DTW_FLAG_NO_QUEUE = 2
@@ -42,7 +42,8 @@ class dtw_dataset(ctypes.Structure):
 
 class dtw_options(ctypes.Structure):
     _fields_ = [("dtype", ctypes.c_int32), ("accum", ctypes.c_int32), ("kernel", ctypes.c_int32),
-                ("flags", ctypes.c_int32), ("rows_per_lane", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+                ("flags", ctypes.c_int32), ("rows_per_lane", ctypes.c_int32), ("stream", ctypes.c_void_p),
+                ("k_begin", ctypes.c_int64), ("k_end", ctypes.c_int64)]
 
 
 class dtw_pair(ctypes.Structure):
@@ -135,7 +136,7 @@ def _make_dataset(series, lengths, offsets, window, out):
     return d, (ln, off)
 
 
-def _options(dtype="f32", accum="plain", kernel="auto", flags=0, stream=None, rows_per_lane=0):
+def _options(dtype="f32", accum="auto", kernel="auto", flags=0, stream=None, rows_per_lane=0, k_range=(0, 0)):
     o = dtw_options()
     o.dtype = DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
     o.accum = ACCUM[accum] if isinstance(accum, str) else int(accum)
@@ -143,22 +144,26 @@ def _options(dtype="f32", accum="plain", kernel="auto", flags=0, stream=None, ro
     o.flags = int(flags)
     o.rows_per_lane = int(rows_per_lane)
     o.stream = _stream_handle(stream) if stream is not False else ctypes.c_void_p(0)
+    o.k_begin, o.k_end = int(k_range[0]), int(k_range[1])
     return o
 
 
 def dtw_pairwise(series, lengths, offsets, N, window, out_condensed):
-    """Short form of the C ABI: FP32 device series, condensed FP32 device output (blocking)."""
+    """Short form of the C ABI: FP32 device series, condensed FP32 device output, enqueued on the default stream."""
     ln, off = _host_arrays(lengths, offsets)
     _check(load().dtw_pairwise(ctypes.c_void_p(series.data_ptr()), ln.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                                off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), int(N), int(window),
                                ctypes.c_void_p(out_condensed.data_ptr())))
 
 
-def dtw_pairwise_ex(series, lengths, offsets, window, out_condensed, dtype="f32", accum="plain", kernel="auto",
-                    stream=None, rows_per_lane=0, queue=True):
-    """One dataset with options (blocking).  `series` holds f32, bf16 (as int16/uint16 bits) or f16 values."""
+def dtw_pairwise_ex(series, lengths, offsets, window, out_condensed, dtype="f32", accum="auto", kernel="auto",
+                    stream=None, rows_per_lane=0, queue=True, k_range=(0, 0)):
+    """One dataset with options, enqueued on `stream` (None = torch's current stream).
+
+    `series` holds f32, bf16 (as int16/uint16 bits) or f16 values; k_range = (k_begin, k_end) restricts the
+    written condensed entries (0, 0 = all)."""
     d, keep = _make_dataset(series, lengths, offsets, window, out_condensed)
-    o = _options(dtype, accum, kernel, 0 if queue else DTW_FLAG_NO_QUEUE, stream, rows_per_lane)
+    o = _options(dtype, accum, kernel, 0 if queue else DTW_FLAG_NO_QUEUE, stream, rows_per_lane, k_range)
     _check(load().dtw_pairwise_ex(ctypes.byref(d), ctypes.byref(o)))
     del keep
 
@@ -170,8 +175,8 @@ class Plan:
     The tensors must stay alive, at the same address, while the plan exists.
     """
 
-    def __init__(self, datasets, dtype="f32", accum="plain", kernel="auto", timing=False, rows_per_lane=0,
-                 queue=True, autotune=False):
+    def __init__(self, datasets, dtype="f32", accum="auto", kernel="auto", timing=False, rows_per_lane=0,
+                 queue=True, autotune=False, k_range=(0, 0)):
         self._lib = load()
         arr = (dtw_dataset * max(1, len(datasets)))()
         self._keep = []
@@ -181,7 +186,7 @@ class Plan:
             self._keep.append((keep, series, out))
         flags = ((DTW_FLAG_TIMING if timing else 0) | (0 if queue else DTW_FLAG_NO_QUEUE)
                  | (DTW_FLAG_AUTOTUNE if autotune else 0))
-        o = _options(dtype, accum, kernel, flags, False, rows_per_lane)
+        o = _options(dtype, accum, kernel, flags, False, rows_per_lane, k_range)
         self._h = ctypes.c_void_p()
         _check(self._lib.dtw_plan_create(ctypes.byref(self._h), arr, len(datasets), ctypes.byref(o)))
 
@@ -225,12 +230,12 @@ def _pair_array(pairs):
     return a, a.ctypes.data_as(ctypes.POINTER(dtw_pair))
 
 
-def dtw_pairs(series, lengths, offsets, window, pairs, out, dtype="f32", accum="plain", kernel="auto",
-              stream=None, queue=True):
-    """Blocking pair-list evaluation: out[k] = DTW(series pairs[k][0], series pairs[k][1])."""
+def dtw_pairs(series, lengths, offsets, window, pairs, out, dtype="f32", accum="auto", kernel="auto",
+              stream=None, queue=True, k_range=(0, 0)):
+    """Pair-list evaluation enqueued on `stream`: out[k] = DTW(series pairs[k][0], series pairs[k][1])."""
     d, keep = _make_dataset(series, lengths, offsets, window, None)
     arr, ptr = _pair_array(pairs)
-    o = _options(dtype, accum, kernel, 0 if queue else DTW_FLAG_NO_QUEUE, stream)
+    o = _options(dtype, accum, kernel, 0 if queue else DTW_FLAG_NO_QUEUE, stream, 0, k_range)
     _check(load().dtw_pairs(ctypes.byref(d), ptr, ctypes.c_int64(len(arr)),
                             ctypes.c_void_p(out.data_ptr() if out is not None else 0), ctypes.byref(o)))
     del keep
@@ -239,7 +244,7 @@ def dtw_pairs(series, lengths, offsets, window, pairs, out, dtype="f32", accum="
 class PairPlan(Plan):
     """dtw_plan_create_pairs: a plan over an explicit pair list of one dataset."""
 
-    def __init__(self, series, lengths, offsets, window, pairs, out, dtype="f32", accum="plain", kernel="auto",
+    def __init__(self, series, lengths, offsets, window, pairs, out, dtype="f32", accum="auto", kernel="auto",
                  timing=False, queue=True, autotune=False):
         self._lib = load()
         d, keep = _make_dataset(series, lengths, offsets, window, None)
@@ -315,8 +320,8 @@ def device_series(ds, device="cuda"):
     return t.to(device)
 
 
-def pairs_of(ds, pairs, accum="plain", kernel="auto", device="cuda"):
-    """DTW of listed pairs of a synth.Dataset on the GPU, as a torch tensor (blocking)."""
+def pairs_of(ds, pairs, accum="auto", kernel="auto", device="cuda"):
+    """DTW of listed pairs of a synth.Dataset on the GPU, as a torch tensor (enqueued on the current stream)."""
     import torch
     series = device_series(ds, device)
     out = torch.full((max(1, len(pairs)),), float("nan"), dtype=torch.float32, device=device)
@@ -324,12 +329,12 @@ def pairs_of(ds, pairs, accum="plain", kernel="auto", device="cuda"):
     return out[:len(pairs)]
 
 
-def pairwise(ds, accum="plain", kernel="auto", device="cuda", out=None, rows_per_lane=0, queue=True):
-    """Condensed DTW matrix of a synth.Dataset on the GPU, returned as a torch tensor (blocking)."""
+def pairwise(ds, accum="auto", kernel="auto", device="cuda", out=None, rows_per_lane=0, queue=True, k_range=(0, 0)):
+    """Condensed DTW matrix of a synth.Dataset on the GPU, as a torch tensor (enqueued on the current stream)."""
     import torch
     series = device_series(ds, device)
     if out is None:
         out = torch.full((max(0, ds.n_pairs),), float("nan"), dtype=torch.float32, device=device)
     dtw_pairwise_ex(series, ds.lengths, ds.offsets, ds.window, out, dtype=ds.dtype, accum=accum, kernel=kernel,
-                    rows_per_lane=rows_per_lane, queue=queue)
+                    rows_per_lane=rows_per_lane, queue=queue, k_range=k_range)
     return out

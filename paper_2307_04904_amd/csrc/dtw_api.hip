@@ -17,6 +17,13 @@
 //    only its window), whichever a step-count cost model finds cheaper.
 //    Items are grouped by kernel instance and each group is sorted by
 //    decreasing cost, so the longest pairs start first.
+//  * accumulation: AUTO gives each pair plain FP32 sums when its longest
+//    warping path (n+m-1 cells) has at most 2048 cells and rebased FP32 sums
+//    beyond, where plain sums approach the 1e-5 accuracy target.
+//  * a condensed sub-range [k_begin, k_end) restricts a plan to those output
+//    entries: lane-band datasets are then tiled by rows of the condensed
+//    matrix (runs of up to 64 consecutive partners j of one series i), the
+//    others enumerate only the pairs of the range.
 #include "dtw_internal.h"
 #include "dtwmi.h"
 
@@ -25,6 +32,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <set>
 #include <new>
 #include <string>
@@ -89,6 +97,28 @@ int64_t condensed_host(int32_t i, int32_t j, int32_t N) {
     return a * N - a * (a + 1) / 2 + (b - a - 1);
 }
 
+// Accumulation of one pair (AccMode) under the public mode.
+constexpr int64_t kAutoPlainMaxPath = 2048;  // longest path summed plainly under AUTO
+int pair_acc(int accum, int64_t n, int64_t m) {
+    switch (accum) {
+        case DTW_ACC_PLAIN: return kAccPlain;
+        case DTW_ACC_KAHAN: return kAccKahan;
+        case DTW_ACC_FP64: return kAccF64;
+        case DTW_ACC_REBASED: return kAccRebased;
+        default: return n + m - 1 <= kAutoPlainMaxPath ? kAccPlain : kAccRebased;
+    }
+}
+// Modes with the plain FP32 cell, which the lane-band and cyclic kernels run.
+bool plain_cell(int acc) { return acc == kAccPlain || acc == kAccRebased; }
+const char *acc_name(int acc) {
+    switch (acc) {
+        case kAccKahan: return "kahan";
+        case kAccF64: return "fp64";
+        case kAccRebased: return "rebased";
+        default: return "plain";
+    }
+}
+
 int64_t effective_band(int32_t w, int32_t n, int32_t m) {
     if (w < 0) return -1;
     const int64_t d = n > m ? (int64_t)n - m : (int64_t)m - n;
@@ -98,12 +128,14 @@ int64_t effective_band(int32_t w, int32_t n, int32_t m) {
 
 struct LaneGroup {
     int W;
+    bool rebased;
     int64_t begin, count;
 };
 
 struct WaveGroup {
     StripShape shape;  // G == 0: cyclic kernel with H = shape.H
     bool banded;
+    int acc;           // AccMode
     int64_t begin, count;
     int slots = 0;           // resident workgroups of the kernel (queue mode)
     int64_t band_cells = 0;  // admissible cells of the group's pairs
@@ -232,6 +264,7 @@ struct WavePair {
     int32_t d, shorter, longer, n, m;
     int32_t b;     // effective band, -1 = none
     int64_t slot;  // output index in the dataset's output
+    int32_t acc;   // AccMode of the pair
 };
 
 // Kernel instance of a wavefront pair: a strip shape, or (G == 0) the cyclic
@@ -243,8 +276,7 @@ struct Choice {
     bool operator<(const Choice &o) const { return H != o.H ? H < o.H : G < o.G; }
 };
 
-int64_t choice_cost(int accum, Choice c, const WavePair &w) {
-    (void)accum;
+int64_t choice_cost(Choice c, const WavePair &w) {
     return c.cyclic() ? cyclic_cost(c.H, w.m, w.n) : strip_cost(StripShape{c.H, c.G}, w.n, w.m, w.b >= 0);
 }
 
@@ -253,14 +285,16 @@ int64_t choice_steps_cells(Choice c, const WavePair &w) {  // cells swept, paddi
                       : (int64_t)64 * c.G * c.H * strip_steps(StripShape{c.H, c.G}, w.n, w.m);
 }
 
-// The cost model's choice for a pair (H == 0 if no instance fits).
-Choice model_choice(int accum, int kernel, int force_h, const WavePair &w) {
+// The cost model's choice for a pair (H == 0 if no instance fits), for the
+// pair's accumulation (rebased instances cost the same as plain ones within a
+// few per cent, so one model serves both).
+Choice model_choice(int kernel, int force_h, const WavePair &w) {
     int64_t cyc_cost = 0;
-    const int cyc_h = (accum == DTW_ACC_PLAIN && w.b >= 0 && kernel != DTW_KERNEL_WAVE)
+    const int cyc_h = (plain_cell(w.acc) && w.b >= 0 && kernel != DTW_KERNEL_WAVE)
                           ? pick_cyclic(w.m, w.n, w.b, force_h, &cyc_cost)
                           : 0;
     const StripShape sh =
-        kernel == DTW_KERNEL_CYCLIC && cyc_h ? StripShape{0, 0} : pick_strip(accum, w.n, w.m, w.b >= 0, force_h);
+        kernel == DTW_KERNEL_CYCLIC && cyc_h ? StripShape{0, 0} : pick_strip(w.acc, w.n, w.m, w.b >= 0, force_h);
     if (cyc_h && (!sh.H || cyc_cost < strip_cost(sh, w.n, w.m, w.b >= 0))) return Choice{cyc_h, 0};
     return Choice{sh.H, sh.G};
 }
@@ -283,6 +317,7 @@ int64_t half_octave_lo(int h) { return h & 1 ? (int64_t(3) << (h / 2)) / 2 : int
 // Autotuning record of one (shorter length, longer length, band) bucket.
 struct TunedBucket {
     int n_ho, m_ho, b_ho;  // half-octave buckets (b_ho of b+1; -1 = no window)
+    int acc;               // AccMode of the bucket's pairs
     int64_t pairs;
     Choice model, chosen;
     std::vector<std::pair<Choice, float>> us_per_pair;  // measured candidates
@@ -292,7 +327,7 @@ struct TunedBucket {
 
 struct dtw_plan_s {
     int device = 0;
-    int dtype = 0, accum = 0, kernel = 0, flags = 0;
+    int dtype = 0, accum = 0, kernel = 0, flags = 0;  // accum: the public dtw_accum
     int32_t nseries = 0;
     void *dev_block = nullptr;  // one allocation holding everything below
     size_t dev_bytes = 0;
@@ -325,14 +360,19 @@ namespace {
 int validate_options(const dtw_options *opt) {
     if (!opt) return DTW_OK;
     if (opt->dtype < DTW_F32 || opt->dtype > DTW_F16) return fail(DTW_ERR_INVALID_ARG, "unknown dtype %d", opt->dtype);
-    if (opt->accum < DTW_ACC_PLAIN || opt->accum > DTW_ACC_FP64)
+    if (opt->accum < DTW_ACC_AUTO || opt->accum > DTW_ACC_REBASED)
         return fail(DTW_ERR_INVALID_ARG, "unknown accumulation mode %d", opt->accum);
     if (opt->kernel < DTW_KERNEL_AUTO || opt->kernel > DTW_KERNEL_CYCLIC)
         return fail(DTW_ERR_INVALID_ARG, "unknown kernel family %d", opt->kernel);
     if (opt->rows_per_lane < 0 || opt->rows_per_lane > 64)
         return fail(DTW_ERR_INVALID_ARG, "rows_per_lane=%d outside 0..64", opt->rows_per_lane);
-    if (opt->kernel == DTW_KERNEL_CYCLIC && opt->accum != DTW_ACC_PLAIN)
-        return fail(DTW_ERR_UNSUPPORTED, "the cyclic kernel needs PLAIN accumulation");
+    if ((opt->kernel == DTW_KERNEL_CYCLIC || opt->kernel == DTW_KERNEL_LANE) &&
+        (opt->accum == DTW_ACC_KAHAN || opt->accum == DTW_ACC_FP64))
+        return fail(DTW_ERR_UNSUPPORTED, "the %s kernel needs AUTO, PLAIN or REBASED accumulation",
+                    opt->kernel == DTW_KERNEL_CYCLIC ? "cyclic" : "lane-band");
+    if (opt->k_begin < 0 || (opt->k_end > 0 && opt->k_end < opt->k_begin))
+        return fail(DTW_ERR_INVALID_ARG, "output range [%lld, %lld) is invalid", (long long)opt->k_begin,
+                    (long long)opt->k_end);
     if (opt->flags & ~(DTW_FLAG_TIMING | DTW_FLAG_NO_QUEUE | DTW_FLAG_AUTOTUNE))
         return fail(DTW_ERR_INVALID_ARG, "unknown flags 0x%x", opt->flags);
     return DTW_OK;
@@ -376,7 +416,7 @@ constexpr int kTuneMaxItems = 16384;  // items of one timing launch (sample repe
 // Instances that can run every pair of a bucket: the cyclic heights that fit
 // all of them and the two smallest strip shapes that hold the longest shorter
 // series (strips only when the plan's kernel family allows them).
-std::vector<Choice> bucket_candidates(int accum, int kernel, int force_h, const std::vector<WavePair> &wp,
+std::vector<Choice> bucket_candidates(int acc, int kernel, int force_h, const std::vector<WavePair> &wp,
                                       const std::vector<int64_t> &idx) {
     int max_n = 0;
     bool all_banded = true;
@@ -385,7 +425,7 @@ std::vector<Choice> bucket_candidates(int accum, int kernel, int force_h, const 
         all_banded = all_banded && wp[k].b >= 0;
     }
     std::vector<Choice> out;
-    if (accum == DTW_ACC_PLAIN && all_banded && kernel != DTW_KERNEL_WAVE) {
+    if (plain_cell(acc) && all_banded && kernel != DTW_KERNEL_WAVE) {
         int hs[32];
         const int kc = cyclic_shapes(hs, 32);
         for (int i = 0; i < kc && i < 32; ++i) {
@@ -397,7 +437,7 @@ std::vector<Choice> bucket_candidates(int accum, int kernel, int force_h, const 
     }
     if (!(kernel == DTW_KERNEL_CYCLIC && !out.empty())) {
         StripShape shapes[64];
-        const int ks = strip_shapes(accum, shapes, 64);
+        const int ks = strip_shapes(acc, shapes, 64);
         int taken = 0;
         for (int i = 0; i < ks && i < 64 && taken < 2; ++i)
             if (64 * shapes[i].H * shapes[i].G >= max_n && (force_h <= 0 || shapes[i].H == force_h)) {
@@ -414,12 +454,11 @@ std::vector<Choice> bucket_candidates(int accum, int kernel, int force_h, const 
 // the device once (its resident workgroups), so it measures throughput, not
 // the latency of a few pairs.  The kernels write the sampled pairs' results
 // into the outputs, which every execute overwrites.
-int autotune(dtw_plan p, const std::vector<WavePair> &wp, std::vector<Choice> &choice, int accum, int kernel,
-             int force_h) {
-    std::map<std::tuple<int, int, int>, std::vector<int64_t>> buckets;
+int autotune(dtw_plan p, const std::vector<WavePair> &wp, std::vector<Choice> &choice, int kernel, int force_h) {
+    std::map<std::tuple<int, int, int, int>, std::vector<int64_t>> buckets;
     for (size_t k = 0; k < wp.size(); ++k)
         buckets[std::make_tuple(half_octave(wp[k].n), half_octave(wp[k].m),
-                                wp[k].b < 0 ? -1 : half_octave((int64_t)wp[k].b + 1))]
+                                wp[k].b < 0 ? -1 : half_octave((int64_t)wp[k].b + 1), wp[k].acc)]
             .push_back((int64_t)k);
 
     hipStream_t s = nullptr;
@@ -436,7 +475,8 @@ int autotune(dtw_plan p, const std::vector<WavePair> &wp, std::vector<Choice> &c
 
     for (auto it = buckets.begin(); rc == DTW_OK && it != buckets.end(); ++it) {
         const std::vector<int64_t> &idx = it->second;
-        std::vector<Choice> cands = bucket_candidates(accum, kernel, force_h, wp, idx);
+        const int acc = std::get<3>(it->first);
+        std::vector<Choice> cands = bucket_candidates(acc, kernel, force_h, wp, idx);
         if (cands.size() < 2) continue;  // nothing to choose
         std::vector<int64_t> sample;
         const int64_t ns = std::min<int64_t>(kTuneSample, (int64_t)idx.size());
@@ -444,7 +484,7 @@ int autotune(dtw_plan p, const std::vector<WavePair> &wp, std::vector<Choice> &c
         std::vector<std::pair<int64_t, Choice>> ranked;
         for (const Choice &c : cands) {
             int64_t cost = 0;
-            for (int64_t k : sample) cost += choice_cost(accum, c, wp[k]);
+            for (int64_t k : sample) cost += choice_cost(c, wp[k]);
             ranked.push_back({cost, c});
         }
         std::stable_sort(ranked.begin(), ranked.end(),
@@ -453,18 +493,20 @@ int autotune(dtw_plan p, const std::vector<WavePair> &wp, std::vector<Choice> &c
                          });
         if (ranked.size() > (size_t)kTuneCandidates) ranked.resize(kTuneCandidates);
         const bool banded = std::get<2>(it->first) >= 0;
-        TunedBucket tb{std::get<0>(it->first), std::get<1>(it->first), std::get<2>(it->first),
+        TunedBucket tb{std::get<0>(it->first), std::get<1>(it->first), std::get<2>(it->first), acc,
                        (int64_t)idx.size(), ranked[0].second, ranked[0].second, {}};
         float best = 0.0f;
         for (const auto &rc_pair : ranked) {
             const Choice c = rc_pair.second;
-            const int slots = c.cyclic() ? cyclic_resident(c.H) : strip_resident(accum, StripShape{c.H, c.G}, banded);
+            const int slots = c.cyclic() ? cyclic_resident(c.H, acc == kAccRebased)
+                                         : strip_resident(acc, StripShape{c.H, c.G}, banded);
             const int64_t T = std::min<int64_t>(kTuneMaxItems, std::max<int64_t>((int64_t)sample.size(), slots));
             for (int64_t t = 0; t < T; ++t) host[(size_t)t] = make_item(c, wp[sample[(size_t)(t % ns)]]);
             e = hipMemcpy(d_items, host.data(), (size_t)T * sizeof(WaveItem), hipMemcpyHostToDevice);
             auto run = [&]() {
-                return c.cyclic() ? launch_cyclic(c.H, p->ws, p->d_ser, p->d_ds, d_items, (unsigned)T, nullptr, 0, s)
-                                  : launch_strip(accum, StripShape{c.H, c.G}, banded, p->ws, p->d_ser, p->d_ds,
+                return c.cyclic() ? launch_cyclic(c.H, acc == kAccRebased, p->ws, p->d_ser, p->d_ds, d_items,
+                                                  (unsigned)T, nullptr, 0, s)
+                                  : launch_strip(acc, StripShape{c.H, c.G}, banded, p->ws, p->d_ser, p->d_ds,
                                                  d_items, (unsigned)T, nullptr, 0, s);
             };
             if (e == hipSuccess && !warmed.count({c, banded})) {  // first launch of an instance loads its code
@@ -540,10 +582,12 @@ int plan_build(dtw_plan *plan_out, const dtw_dataset *ds, int32_t n_datasets, co
     int rc = DTW_OK;
 
     const int dtype = opt ? opt->dtype : DTW_F32;
-    const int accum = opt ? opt->accum : DTW_ACC_PLAIN;
+    const int accum = opt ? opt->accum : DTW_ACC_AUTO;
     const int kernel = opt ? opt->kernel : DTW_KERNEL_AUTO;
     const int flags = opt ? opt->flags : 0;
     const int force_h = opt ? opt->rows_per_lane : 0;
+    const int64_t k_begin = opt ? opt->k_begin : 0;
+    const int64_t k_end_opt = opt ? opt->k_end : 0;
 
     // ---- host-side planning (no HIP calls) ----
     std::vector<SeriesSrc> src;
@@ -551,7 +595,7 @@ int plan_build(dtw_plan *plan_out, const dtw_dataset *ds, int32_t n_datasets, co
     std::vector<DatasetInfo> dsi;
     std::vector<LaneItem> lane_items;
     std::vector<LanePartner> partners;  // explicit partners of pair-list lane items
-    std::map<int, std::vector<LaneItem>> lane_by_w;
+    std::map<std::pair<int, bool>, std::vector<LaneItem>> lane_by_w;  // (W, rebased)
     std::vector<WavePair> wpairs;
     dtw_plan_stats st{};
     size_t ws_floats = 0;
@@ -563,7 +607,11 @@ int plan_build(dtw_plan *plan_out, const dtw_dataset *ds, int32_t n_datasets, co
         info.N = D.N;
         info.window = D.window;
         info.series_base = static_cast<int32_t>(ser.size());
-        if (D.N < (req ? 1 : 2) || (req && req->n == 0)) {
+        // output entries [k0, k1) of this dataset
+        const int64_t n_out = req ? req->n : (D.N >= 2 ? (int64_t)D.N * (D.N - 1) / 2 : 0);
+        const int64_t k1 = k_end_opt > 0 ? std::min(k_end_opt, n_out) : n_out;
+        const int64_t k0 = std::min(k_begin, k1);
+        if (D.N < (req ? 1 : 2) || k1 <= k0) {
             info.L = -1;
             dsi.push_back(info);
             continue;
@@ -581,21 +629,25 @@ int plan_build(dtw_plan *plan_out, const dtw_dataset *ds, int32_t n_datasets, co
         }
         info.L = uniform ? D.lengths[0] : -1;
         dsi.push_back(info);
-        const int64_t npairs = req ? req->n : (int64_t)D.N * (D.N - 1) / 2;
+        const int64_t npairs = k1 - k0;
+        const bool full = k0 == 0 && k1 == n_out;
         st.pairs += npairs;
 
         // Kernel family for this dataset.
         int lane_w = 0;
-        if (uniform && accum == DTW_ACC_PLAIN) {
+        const int lane_acc = uniform ? pair_acc(accum, D.lengths[0], D.lengths[0]) : kAccPlain;
+        if (uniform && plain_cell(lane_acc)) {
             const int32_t L = D.lengths[0];
             const int32_t b = (D.window < 0 || D.window >= L - 1) ? L - 1 : D.window;
             if (lane_width_supported(2 * b + 1)) lane_w = 2 * b + 1;
         }
         if (kernel == DTW_KERNEL_LANE && !lane_w)
             return fail(DTW_ERR_UNSUPPORTED,
-                        "dataset %d: the lane-band kernel needs equal lengths, PLAIN accumulation and 2*w+1 <= %d",
+                        "dataset %d: the lane-band kernel needs equal lengths, PLAIN or REBASED accumulation and "
+                        "2*w+1 <= %d",
                         d, kLaneMaxW);
         if (kernel == DTW_KERNEL_WAVE || kernel == DTW_KERNEL_CYCLIC) lane_w = 0;
+        const auto lane_key = std::make_pair(lane_w, lane_acc == kAccRebased);
 
         if (lane_w && req) {
             // Each listed pair goes to the tile of whichever of its series is
@@ -605,12 +657,12 @@ int plan_build(dtw_plan *plan_out, const dtw_dataset *ds, int32_t n_datasets, co
             const int32_t L = D.lengths[0], b = (lane_w - 1) / 2;
             st.band_cells += npairs * band_cells(L, L, b >= L - 1 ? -1 : b);
             std::vector<int64_t> count(D.N, 0);
-            for (int64_t k = 0; k < req->n; ++k) {
+            for (int64_t k = k0; k < k1; ++k) {
                 ++count[req->pairs[k].i];
                 ++count[req->pairs[k].j];
             }
             std::map<int32_t, std::vector<LanePartner>> by_a;
-            for (int64_t k = 0; k < req->n; ++k) {
+            for (int64_t k = k0; k < k1; ++k) {
                 const int32_t i = req->pairs[k].i, j = req->pairs[k].j;
                 const bool on_i = count[i] > count[j] || (count[i] == count[j] && i <= j);
                 by_a[on_i ? i : j].push_back(LanePartner{on_i ? j : i, 0, k});
@@ -618,11 +670,11 @@ int plan_build(dtw_plan *plan_out, const dtw_dataset *ds, int32_t n_datasets, co
             for (auto &kv : by_a)
                 for (size_t s0 = 0; s0 < kv.second.size(); s0 += 64) {
                     const int32_t cnt = (int32_t)std::min<size_t>(64, kv.second.size() - s0);
-                    lane_by_w[lane_w].push_back(LaneItem{d, kv.first, 0, cnt, (int64_t)partners.size()});
+                    lane_by_w[lane_key].push_back(LaneItem{d, kv.first, 0, cnt, (int64_t)partners.size()});
                     partners.insert(partners.end(), kv.second.begin() + s0, kv.second.begin() + s0 + cnt);
                     st.computed_cells += (int64_t)64 * L * lane_w;
                 }
-        } else if (lane_w) {
+        } else if (lane_w && full) {
             const int32_t N = D.N, L = D.lengths[0], b = (lane_w - 1) / 2;
             st.band_cells += npairs * band_cells(L, L, b >= L - 1 ? -1 : b);
             for (int32_t a = 0; a < N; ++a) {
@@ -630,13 +682,35 @@ int plan_build(dtw_plan *plan_out, const dtw_dataset *ds, int32_t n_datasets, co
                 if (N % 2 == 0 && a < N / 2) h = N / 2;
                 for (int32_t d0 = 1; d0 <= h; d0 += 64) {
                     const int32_t cnt = std::min(64, h - d0 + 1);
-                    lane_by_w[lane_w].push_back(LaneItem{d, a, d0, cnt, -1});
+                    lane_by_w[lane_key].push_back(LaneItem{d, a, d0, cnt, -1});
+                    st.computed_cells += (int64_t)64 * L * lane_w;
+                }
+            }
+        } else if (lane_w) {
+            // a part of the condensed matrix: runs of up to 64 consecutive
+            // partners j > i of one series i (partner a + d0 + lane, no wrap)
+            const int32_t N = D.N, L = D.lengths[0], b = (lane_w - 1) / 2;
+            st.band_cells += npairs * band_cells(L, L, b >= L - 1 ? -1 : b);
+            int64_t row0 = 0;  // condensed index of pair (i, i+1)
+            for (int32_t i = 0; i < N - 1 && row0 < k1; row0 += N - 1 - i, ++i) {
+                const int64_t lo = std::max(k0, row0), hi = std::min(k1, row0 + (N - 1 - i));
+                for (int64_t k = lo; k < hi; k += 64) {
+                    const int32_t cnt = (int32_t)std::min<int64_t>(64, hi - k);
+                    lane_by_w[lane_key].push_back(LaneItem{d, i, (int32_t)(k - row0 + 1), cnt, -1});
                     st.computed_cells += (int64_t)64 * L * lane_w;
                 }
             }
         } else {
-            const int64_t n_list = req ? req->n : 0;
-            for (int64_t k = 0, i = 0, j = 1; req ? k < n_list : i < D.N - 1; ++k) {
+            // pairs of the range: list positions, or condensed indices walked row by row
+            int64_t i = 0, j = 1, row0 = 0;
+            if (!req) {
+                while (row0 + (D.N - 1 - i) <= k0) {
+                    row0 += D.N - 1 - i;
+                    ++i;
+                }
+                j = i + 1 + (k0 - row0);
+            }
+            for (int64_t k = k0; k < k1; ++k) {
                 if (req) {
                     i = req->pairs[k].i;
                     j = req->pairs[k].j;
@@ -645,11 +719,12 @@ int plan_build(dtw_plan *plan_out, const dtw_dataset *ds, int32_t n_datasets, co
                     const int32_t ni = D.lengths[i], nj = D.lengths[j];
                     const bool swap = nj < ni;
                     WavePair w{d, (int32_t)(swap ? j : i), (int32_t)(swap ? i : j), std::min(ni, nj),
-                               std::max(ni, nj), 0, 0};
-                    w.slot = req ? k : condensed_host((int32_t)i, (int32_t)j, D.N);
+                               std::max(ni, nj), 0, 0, 0};
+                    w.slot = k;
                     w.b = static_cast<int32_t>(effective_band(D.window, w.n, w.m));
+                    w.acc = pair_acc(accum, w.n, w.m);
                     st.band_cells += band_cells(w.n, w.m, w.b);
-                    if (!model_choice(accum, kernel, force_h, w).H) {
+                    if (!model_choice(kernel, force_h, w).H) {
                         if (force_h > 0)
                             return fail(DTW_ERR_UNSUPPORTED,
                                         "dataset %d: pair (%d,%d) (%d x %d points, band %d): no kernel with "
@@ -657,7 +732,7 @@ int plan_build(dtw_plan *plan_out, const dtw_dataset *ds, int32_t n_datasets, co
                                         d, (int)i, (int)j, w.n, w.m, w.b, force_h);
                         return fail(DTW_ERR_UNSUPPORTED,
                                     "dataset %d: pair (%d,%d) has both series longer than %d points", d, (int)i,
-                                    (int)j, max_strip_rows(accum));
+                                    (int)j, max_strip_rows(w.acc));
                     }
                     wpairs.push_back(w);
                 }
@@ -677,7 +752,8 @@ int plan_build(dtw_plan *plan_out, const dtw_dataset *ds, int32_t n_datasets, co
     p->flags = flags;
     p->nseries = static_cast<int32_t>(ser.size());
     for (auto &kv : lane_by_w) {
-        p->lane_groups.push_back(LaneGroup{kv.first, (int64_t)lane_items.size(), (int64_t)kv.second.size()});
+        p->lane_groups.push_back(
+            LaneGroup{kv.first.first, kv.first.second, (int64_t)lane_items.size(), (int64_t)kv.second.size()});
         lane_items.insert(lane_items.end(), kv.second.begin(), kv.second.end());
     }
     st.n_lane_items = static_cast<int32_t>(lane_items.size());
@@ -743,9 +819,9 @@ int plan_build(dtw_plan *plan_out, const dtw_dataset *ds, int32_t n_datasets, co
 
     // ---- kernel instance of every wavefront pair: cost model, or measured ----
     std::vector<Choice> choice(wpairs.size());
-    for (size_t k = 0; k < wpairs.size(); ++k) choice[k] = model_choice(accum, kernel, force_h, wpairs[k]);
+    for (size_t k = 0; k < wpairs.size(); ++k) choice[k] = model_choice(kernel, force_h, wpairs[k]);
     if ((flags & DTW_FLAG_AUTOTUNE) && !wpairs.empty()) {
-        rc = autotune(p, wpairs, choice, accum, kernel, force_h);
+        rc = autotune(p, wpairs, choice, kernel, force_h);
         if (rc) {
             destroy_plan(p);
             return rc;
@@ -754,9 +830,9 @@ int plan_build(dtw_plan *plan_out, const dtw_dataset *ds, int32_t n_datasets, co
         for (const TunedBucket &t : p->tuned) st.n_tuned_changed += t.chosen == t.model ? 0 : 1;
     }
 
-    // Group by kernel instance (H, G, banded); inside a group costlier pairs
-    // first, groups in decreasing order of their costliest pair.
-    using Kind = std::tuple<int, int, bool>;  // H, G, banded
+    // Group by kernel instance (H, G, banded, accumulation); inside a group
+    // costlier pairs first, groups in decreasing order of their costliest pair.
+    using Kind = std::tuple<int, int, bool, int>;  // H, G, banded, AccMode
     std::map<Kind, std::vector<std::pair<int64_t, WaveItem>>> wave_by_kind;
     std::map<Kind, std::pair<int64_t, int64_t>> cells_by_kind;  // admissible, swept
     for (size_t k = 0; k < wpairs.size(); ++k) {
@@ -765,8 +841,8 @@ int plan_build(dtw_plan *plan_out, const dtw_dataset *ds, int32_t n_datasets, co
         const int64_t swept = choice_steps_cells(c, w);
         st.computed_cells += swept;
         st.n_cyclic_items += c.cyclic() ? 1 : 0;
-        const Kind kind = std::make_tuple(c.H, c.G, c.cyclic() || w.b >= 0);
-        wave_by_kind[kind].push_back({choice_cost(accum, c, w), make_item(c, w)});
+        const Kind kind = std::make_tuple(c.H, c.G, c.cyclic() || w.b >= 0, (int)w.acc);
+        wave_by_kind[kind].push_back({choice_cost(c, w), make_item(c, w)});
         auto &cells = cells_by_kind[kind];
         cells.first += band_cells(w.n, w.m, w.b);
         cells.second += swept;
@@ -791,8 +867,9 @@ int plan_build(dtw_plan *plan_out, const dtw_dataset *ds, int32_t n_datasets, co
         }
         const StripShape sh{std::get<0>(it->first), std::get<1>(it->first)};
         const auto &cells = cells_by_kind[it->first];
-        p->wave_groups.push_back(WaveGroup{sh, std::get<2>(it->first), (int64_t)wave_items.size(), (int64_t)v.size(),
-                                           0, cells.first, cells.second});
+        p->wave_groups.push_back(WaveGroup{sh, std::get<2>(it->first), std::get<3>(it->first),
+                                           (int64_t)wave_items.size(), (int64_t)v.size(), 0, cells.first,
+                                           cells.second});
         for (auto &e2 : v) wave_items.push_back(e2.second);
     }
     if (p->wave_groups.size() > (size_t)kMaxQueues) {
@@ -811,7 +888,8 @@ int plan_build(dtw_plan *plan_out, const dtw_dataset *ds, int32_t n_datasets, co
     p->d_queue = p->n_queue ? reinterpret_cast<unsigned *>(base + o_queue) : nullptr;
     if (use_queue)  // grid of each launch: the workgroups the device holds at once
         for (WaveGroup &g : p->wave_groups)
-            g.slots = g.shape.G == 0 ? cyclic_resident(g.shape.H) : strip_resident(accum, g.shape, g.banded);
+            g.slots = g.shape.G == 0 ? cyclic_resident(g.shape.H, g.acc == kAccRebased)
+                                     : strip_resident(g.acc, g.shape, g.banded);
     st.n_launches = (p->nseries > 0 ? 1 : 0) + (use_queue ? 1 : 0) +
                     (int32_t)(p->lane_groups.size() + p->wave_groups.size());
     p->stats = st;
@@ -849,6 +927,120 @@ int validate_pairs(const dtw_dataset *ds, const dtw_pair *pairs, int64_t n_pairs
         if (pairs[k].i < 0 || pairs[k].i >= ds->N || pairs[k].j < 0 || pairs[k].j >= ds->N)
             return fail(DTW_ERR_INVALID_ARG, "pairs[%lld] = (%d, %d) outside 0..%d", (long long)k, pairs[k].i,
                         pairs[k].j, ds->N - 1);
+    return DTW_OK;
+}
+
+// ---- plan cache of the short forms (dtw_pairwise, dtw_pairwise_ex, dtw_pairs) ----
+// A cached plan is keyed by everything that shapes it except the buffers:
+// device, stream, options, N, window, lengths, offsets (and the pair list).
+// A hit re-points the plan at the call's series and output (k_rebind) and
+// launches it: no allocation, upload or synchronisation.  Enqueueing happens
+// under the cache lock, so the rebind and launches of one call are never
+// interleaved with another call's on the same plan.
+struct CacheKey {
+    int device = 0;
+    void *stream = nullptr;
+    int32_t dtype = 0, accum = 0, kernel = 0, flags = 0, rows = 0;
+    int64_t k_begin = 0, k_end = 0;
+    int32_t N = 0, window = 0;
+    bool list = false;
+    std::vector<int32_t> lengths;
+    std::vector<int64_t> offsets;
+    std::vector<int32_t> pairs;  // i, j interleaved
+
+    bool operator==(const CacheKey &o) const {
+        return device == o.device && stream == o.stream && dtype == o.dtype && accum == o.accum &&
+               kernel == o.kernel && flags == o.flags && rows == o.rows && k_begin == o.k_begin &&
+               k_end == o.k_end && N == o.N && window == o.window && list == o.list && lengths == o.lengths &&
+               offsets == o.offsets && pairs == o.pairs;
+    }
+};
+
+struct CacheEntry {
+    CacheKey key;
+    dtw_plan plan = nullptr;
+    hipEvent_t done = nullptr;  // recorded after the plan's last launch
+    uint64_t used = 0;
+};
+
+constexpr size_t kCacheSize = 8;
+std::mutex g_cache_mu;
+std::vector<CacheEntry> g_cache;
+uint64_t g_cache_tick = 0;
+
+void drop_entry(CacheEntry &c) {
+    if (c.done) {
+        (void)hipEventSynchronize(c.done);  // the plan's last launch has finished
+        (void)hipEventDestroy(c.done);
+    }
+    destroy_plan(c.plan);
+    c.plan = nullptr;
+    c.done = nullptr;
+}
+
+int cached_run(const dtw_dataset &d, const dtw_options *opt, const PairRequest *req) {
+    dtw_options o{};
+    if (opt) o = *opt;
+    o.flags &= DTW_FLAG_NO_QUEUE | DTW_FLAG_AUTOTUNE;  // timing needs the plan API
+    CacheKey key;
+    // Without a device the lookup misses and plan_build reports the request's
+    // host-side errors first (all arguments are checked before any HIP work),
+    // then the failing HIP call.
+    hipError_t e = hipGetDevice(&key.device);
+    if (e != hipSuccess) key.device = -1;
+    key.stream = o.stream;
+    key.dtype = o.dtype;
+    key.accum = o.accum;
+    key.kernel = o.kernel;
+    key.flags = o.flags;
+    key.rows = o.rows_per_lane;
+    key.k_begin = o.k_begin;
+    key.k_end = o.k_end;
+    key.N = d.N;
+    key.window = d.window;
+    key.list = req != nullptr;
+    key.lengths.assign(d.lengths, d.lengths + d.N);
+    key.offsets.assign(d.offsets, d.offsets + d.N);
+    if (req) {
+        key.pairs.resize(2 * (size_t)req->n);
+        for (int64_t k = 0; k < req->n; ++k) {
+            key.pairs[2 * (size_t)k] = req->pairs[k].i;
+            key.pairs[2 * (size_t)k + 1] = req->pairs[k].j;
+        }
+    }
+    hipStream_t s = static_cast<hipStream_t>(o.stream);
+    float *out = req ? req->out : d.out_condensed;
+
+    std::lock_guard<std::mutex> lock(g_cache_mu);
+    CacheEntry *hit = nullptr;
+    for (CacheEntry &c : g_cache)
+        if (c.key == key) hit = &c;
+    if (!hit) {
+        dtw_plan p = nullptr;
+        const int rc = plan_build(&p, &d, 1, &o, req);
+        if (rc) return rc;
+        hipEvent_t done = nullptr;
+        if ((e = hipEventCreateWithFlags(&done, hipEventDisableTiming)) != hipSuccess) {
+            destroy_plan(p);
+            return hip_fail(e, "hipEventCreate");
+        }
+        if (g_cache.size() >= kCacheSize) {  // replace the least recently used plan
+            size_t lru = 0;
+            for (size_t c = 1; c < g_cache.size(); ++c)
+                if (g_cache[c].used < g_cache[lru].used) lru = c;
+            drop_entry(g_cache[lru]);
+            g_cache.erase(g_cache.begin() + (long)lru);
+        }
+        g_cache.push_back(CacheEntry{std::move(key), p, done, 0});
+        hit = &g_cache.back();
+    } else if ((e = launch_rebind(hit->plan->d_src, hit->plan->nseries, d.series, hit->plan->d_ds, out, s)) !=
+               hipSuccess) {
+        return hip_fail(e, "rebind kernel launch");
+    }
+    hit->used = ++g_cache_tick;
+    const int rc = dtw_plan_execute(hit->plan, s);
+    if (rc) return rc;
+    if ((e = hipEventRecord(hit->done, s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
     return DTW_OK;
 }
 
@@ -890,30 +1082,42 @@ int dtw_plan_execute(dtw_plan p, void *stream) {
         return hip_fail(e, "queue reset kernel launch");
     int q = 0;  // queue counter of the next group
     for (const LaneGroup &g : p->lane_groups) {
-        e = launch_lane(g.W, p->ws, p->d_ser, p->d_ds, p->d_lane + g.begin, p->d_partner, (unsigned)g.count, s);
+        e = launch_lane(g.W, g.rebased, p->ws, p->d_ser, p->d_ds, p->d_lane + g.begin, p->d_partner,
+                        (unsigned)g.count, s);
         if (e != hipSuccess) return hip_fail(e, "lane-band kernel launch");
     }
     // Wavefront groups: forked over the plan's streams (round robin, costliest
-    // group first), then joined back into `s`.
+    // group first), then joined back into `s` -- also after a failed launch,
+    // so that `s` never returns (or ends a capture) with work of the plan's
+    // streams outstanding.
     if (p->n_aux && (e = hipEventRecord(p->fork_ev, s)) != hipSuccess) return hip_fail(e, "hipEventRecord (fork)");
-    for (int a = 0; a < p->n_aux; ++a)
-        if ((e = hipStreamWaitEvent(p->aux[a], p->fork_ev, 0)) != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
+    int forked = 0;
+    for (; forked < p->n_aux; ++forked)
+        if ((e = hipStreamWaitEvent(p->aux[forked], p->fork_ev, 0)) != hipSuccess) break;
+    const char *what = e != hipSuccess ? "hipStreamWaitEvent (fork)" : nullptr;
     int k = 0;
-    for (const WaveGroup &g : p->wave_groups) {
+    for (size_t gi = 0; !what && gi < p->wave_groups.size(); ++gi) {
+        const WaveGroup &g = p->wave_groups[gi];
         unsigned *queue = p->d_queue ? p->d_queue + q++ : nullptr;
         hipStream_t gs = p->n_aux ? p->aux[k++ % p->n_aux] : s;
         if (g.shape.G == 0)
-            e = launch_cyclic(g.shape.H, p->ws, p->d_ser, p->d_ds, p->d_wave + g.begin, (unsigned)g.count, queue,
-                              g.slots, gs);
+            e = launch_cyclic(g.shape.H, g.acc == kAccRebased, p->ws, p->d_ser, p->d_ds, p->d_wave + g.begin,
+                              (unsigned)g.count, queue, g.slots, gs);
         else
-            e = launch_strip(p->accum, g.shape, g.banded, p->ws, p->d_ser, p->d_ds, p->d_wave + g.begin,
+            e = launch_strip(g.acc, g.shape, g.banded, p->ws, p->d_ser, p->d_ds, p->d_wave + g.begin,
                              (unsigned)g.count, queue, g.slots, gs);
-        if (e != hipSuccess) return hip_fail(e, "wavefront kernel launch");
+        if (e != hipSuccess) what = "wavefront kernel launch";
     }
-    for (int a = 0; a < p->n_aux; ++a) {
-        if ((e = hipEventRecord(p->join_ev[a], p->aux[a])) != hipSuccess) return hip_fail(e, "hipEventRecord (join)");
-        if ((e = hipStreamWaitEvent(s, p->join_ev[a], 0)) != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
+    const hipError_t e_launch = e;
+    for (int a = 0; a < forked; ++a) {  // join every stream that took the fork
+        hipError_t ej = hipEventRecord(p->join_ev[a], p->aux[a]);
+        if (ej == hipSuccess) ej = hipStreamWaitEvent(s, p->join_ev[a], 0);
+        if (ej != hipSuccess && !what) {
+            what = "join of the plan's streams";
+            e = ej;
+        }
     }
+    if (what) return hip_fail(e_launch != hipSuccess ? e_launch : e, what);
     if (p->ev1) {
         if ((e = hipEventRecord(p->ev1, s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
         p->timed_once = true;
@@ -943,7 +1147,8 @@ int dtw_plan_describe(dtw_plan p, char *buf, int64_t size, int64_t *needed) {
     std::string j = "{\"lane_groups\": [";
     char t[256];
     for (size_t k = 0; k < p->lane_groups.size(); ++k) {
-        snprintf(t, sizeof t, "%s{\"W\": %d, \"items\": %lld}", k ? ", " : "", p->lane_groups[k].W,
+        snprintf(t, sizeof t, "%s{\"W\": %d, \"accum\": \"%s\", \"items\": %lld}", k ? ", " : "",
+                 p->lane_groups[k].W, p->lane_groups[k].rebased ? "rebased" : "plain",
                  (long long)p->lane_groups[k].count);
         j += t;
     }
@@ -951,9 +1156,10 @@ int dtw_plan_describe(dtw_plan p, char *buf, int64_t size, int64_t *needed) {
     for (size_t k = 0; k < p->wave_groups.size(); ++k) {
         const WaveGroup &g = p->wave_groups[k];
         snprintf(t, sizeof t,
-                 "%s{\"kernel\": \"%s\", \"banded\": %s, \"items\": %lld, \"grid\": %lld, \"band_cells\": %lld, "
-                 "\"swept_cells\": %lld}",
-                 k ? ", " : "", choice_name(Choice{g.shape.H, g.shape.G}).c_str(), g.banded ? "true" : "false",
+                 "%s{\"kernel\": \"%s\", \"accum\": \"%s\", \"banded\": %s, \"items\": %lld, \"grid\": %lld, "
+                 "\"band_cells\": %lld, \"swept_cells\": %lld}",
+                 k ? ", " : "", choice_name(Choice{g.shape.H, g.shape.G}).c_str(), acc_name(g.acc),
+                 g.banded ? "true" : "false",
                  (long long)g.count, (long long)(p->n_queue && g.slots > 0 ? std::min<int64_t>(g.slots, g.count) : g.count),
                  (long long)g.band_cells, (long long)g.swept_cells);
         j += t;
@@ -962,11 +1168,11 @@ int dtw_plan_describe(dtw_plan p, char *buf, int64_t size, int64_t *needed) {
     for (size_t k = 0; k < p->tuned.size(); ++k) {
         const TunedBucket &b = p->tuned[k];
         snprintf(t, sizeof t,
-                 "%s{\"n\": [%lld, %lld], \"m\": [%lld, %lld], \"band\": %s, \"pairs\": %lld, \"model\": \"%s\", "
-                 "\"chosen\": \"%s\", \"us_per_pair\": {",
+                 "%s{\"n\": [%lld, %lld], \"m\": [%lld, %lld], \"band\": %s, \"accum\": \"%s\", \"pairs\": %lld, "
+                 "\"model\": \"%s\", \"chosen\": \"%s\", \"us_per_pair\": {",
                  k ? ", " : "", (long long)half_octave_lo(b.n_ho), (long long)half_octave_lo(b.n_ho + 1) - 1,
                  (long long)half_octave_lo(b.m_ho), (long long)half_octave_lo(b.m_ho + 1) - 1,
-                 b.b_ho < 0 ? "null" : "[]", (long long)b.pairs, choice_name(b.model).c_str(),
+                 b.b_ho < 0 ? "null" : "[]", acc_name(b.acc), (long long)b.pairs, choice_name(b.model).c_str(),
                  choice_name(b.chosen).c_str());
         std::string entry = t;
         if (b.b_ho >= 0) {  // band range of the bucket: b + 1 in [lo, hi]
@@ -1007,18 +1213,7 @@ int dtw_pairwise_ex(const dtw_dataset *ds, const dtw_options *opt) {
     if (rc) return rc;
     if ((rc = validate_dataset(*ds, 0))) return rc;
     if (ds->N < 2) return DTW_OK;  // nothing to write, no HIP call
-    dtw_options o{};
-    if (opt) o = *opt;
-    o.flags &= DTW_FLAG_NO_QUEUE | DTW_FLAG_AUTOTUNE;  // timing needs the plan API
-    dtw_plan p = nullptr;
-    rc = dtw_plan_create(&p, ds, 1, &o);
-    if (rc) return rc;
-    rc = dtw_plan_execute(p, o.stream);
-    hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(o.stream));
-    destroy_plan(p);
-    if (rc) return rc;
-    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
-    return DTW_OK;
+    return cached_run(*ds, opt, nullptr);
 }
 
 int dtw_pairs(const dtw_dataset *ds, const dtw_pair *pairs, int64_t n_pairs, float *out, const dtw_options *opt) {
@@ -1026,19 +1221,8 @@ int dtw_pairs(const dtw_dataset *ds, const dtw_pair *pairs, int64_t n_pairs, flo
     int rc = validate_options(opt);
     if (rc || (rc = validate_pairs(ds, pairs, n_pairs, out))) return rc;
     if (n_pairs == 0) return DTW_OK;  // nothing to write, no HIP call
-    dtw_options o{};
-    if (opt) o = *opt;
-    o.flags &= DTW_FLAG_NO_QUEUE | DTW_FLAG_AUTOTUNE;  // timing needs the plan API
-    dtw_plan p = nullptr;
     const PairRequest req{pairs, n_pairs, out};
-    rc = plan_build(&p, ds, 1, &o, &req);
-    if (rc) return rc;
-    rc = dtw_plan_execute(p, o.stream);
-    hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(o.stream));
-    destroy_plan(p);
-    if (rc) return rc;
-    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
-    return DTW_OK;
+    return cached_run(*ds, opt, &req);
 }
 
 int dtw_pairwise(const float *series, const int32_t *lengths, const int64_t *offsets, int32_t N, int32_t window,

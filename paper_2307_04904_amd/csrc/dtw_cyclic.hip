@@ -2,7 +2,8 @@
 // blocks of rows of the longer series cycling over the 64 lanes, each block
 // visiting only the columns its window admits.  Evaluates Eq. (c) of the
 // paper ("Mathematical background") under the window rule of the
-// Introduction, in FP32.
+// Introduction, in FP32 (plain, or rebased: every lane keeps its values
+// relative to a running base of its own, see below).
 #include "dtw_device.h"
 
 namespace dtwmi {
@@ -110,9 +111,22 @@ __device__ __forceinline__ void cyc_events(int s, const CycLane<H> &c, typename 
     }
 }
 
+// Rebased accumulation (RB): the wavefront stores its values relative to a
+// base it shares (true value = stored + base), and every kCycRebaseSteps steps
+// the base moves up to the smallest value on its frontier: every lane's H
+// cells and the boundary values it holds (which carry the last row of a block
+// that has already left its window).  Every path to a cell computed later
+// passes through that frontier and local costs are never negative, so stored
+// values stay between 0 and the true cost and each fused add rounds relative
+// to them instead of the whole cumulative cost: never more than plain sums,
+// on long paths typically an order of magnitude less.  Rows not yet admitted
+// hold values of a wider window, which are no larger than the true ones; they
+// can only lower the minimum, so the base stays a lower bound.
+constexpr int kCycRebaseSteps = 32;  // a multiple of the 4 steps of one loop iteration
+
 // One step.  y0..y3 hold (or are loading) y at this lane's columns of steps
 // s..s+3; a block switch moves the columns by -64, so it reloads them.
-template <int H>
+template <int H, bool RB>
 __device__ __forceinline__ void cyc_step(int s, CycLane<H> &c, typename CycVec<H>::T &x, typename CycVec<H>::T &O,
                                          typename CycVec<H>::T &N, float &up_in, float &diag_in, float &raw_up,
                                          float &raw_diag, float &y0, float &y1, float &y2, float &y3,
@@ -161,7 +175,24 @@ __device__ __forceinline__ void cyc_step(int s, CycLane<H> &c, typename CycVec<H
     up_in = s < c.tphi ? recv : kInf;  // past the previous block's window
 }
 
+// Renormalise the rebased form: the base moves up by the smallest of every
+// lane's rows 0..H-1 and `held`; returns the shift subtracted from every
+// stored value (the difference of the new and the old base as computed).
 template <int H>
+__device__ __forceinline__ float cyc_rebase(typename CycVec<H>::T &A, float held, float &base) {
+    float mn = held;
+#pragma unroll
+    for (int h = 0; h < H; ++h) mn = fminf(mn, A[h]);
+    mn = wave_min(mn);
+    const float nb = base + (mn < kInf ? mn : 0.0f);
+    const float d = nb - base;
+#pragma unroll
+    for (int h = 0; h < H; ++h) A[h] -= d;
+    base = nb;
+    return d;
+}
+
+template <int H, bool RB>
 __device__ __forceinline__ void cyc_item(const WaveItem it, const float *__restrict__ ws,
                                          const SeriesInfo *__restrict__ ser, const DatasetInfo *__restrict__ dsi) {
     typedef typename CycVec<H>::T xvec;
@@ -187,6 +218,7 @@ __device__ __forceinline__ void cyc_item(const WaveItem it, const float *__restr
     float up_in = kInf;
     float diag_in = lane == 0 ? 0.0f : kInf;
     float raw_up = kInf, raw_diag = kInf;  // unmasked values received in the last two steps
+    float base = 0.0f;                     // rebased form only: the wavefront's base
 
     // Four steps per iteration, so that the y prefetch registers rotate by
     // name instead of by copies.
@@ -196,41 +228,49 @@ __device__ __forceinline__ void cyc_item(const WaveItem it, const float *__restr
     for (; s + 3 <= sfinal; s += 4) {
         q2 = c.yl[s + 2];
         q3 = c.yl[s + 3];
-        cyc_step<H>(s, c, x, A, Bv, up_in, diag_in, raw_up, raw_diag, q0, q1, q2, q3, xp, yp, n, m, b,
-                    Qf);
-        cyc_step<H>(s + 1, c, x, Bv, A, up_in, diag_in, raw_up, raw_diag, q1, q2, q3, q0, xp, yp, n, m,
+        cyc_step<H, RB>(s, c, x, A, Bv, up_in, diag_in, raw_up, raw_diag, q0, q1, q2, q3, xp, yp, n, m, b, Qf);
+        cyc_step<H, RB>(s + 1, c, x, Bv, A, up_in, diag_in, raw_up, raw_diag, q1, q2, q3, q0, xp, yp, n, m,
                     b, Qf);
         q0 = c.yl[s + 4];
         q1 = c.yl[s + 5];
-        cyc_step<H>(s + 2, c, x, A, Bv, up_in, diag_in, raw_up, raw_diag, q2, q3, q0, q1, xp, yp, n, m,
+        cyc_step<H, RB>(s + 2, c, x, A, Bv, up_in, diag_in, raw_up, raw_diag, q2, q3, q0, q1, xp, yp, n, m,
                     b, Qf);
-        cyc_step<H>(s + 3, c, x, Bv, A, up_in, diag_in, raw_up, raw_diag, q3, q0, q1, q2, xp, yp, n, m,
+        cyc_step<H, RB>(s + 3, c, x, Bv, A, up_in, diag_in, raw_up, raw_diag, q3, q0, q1, q2, xp, yp, n, m,
                     b, Qf);
+        if constexpr (RB) {
+            if ((s + 4) % kCycRebaseSteps == 0) {
+                const float d = cyc_rebase<H>(A, fminf(fminf(up_in, diag_in), fminf(raw_up, raw_diag)), base);
+                up_in -= d;
+                diag_in -= d;
+                raw_up -= d;
+                raw_diag -= d;
+            }
+        }
     }
     const int rem = sfinal + 1 - s;  // 0..3 steps left
     if (rem >= 1) {
         q2 = c.yl[s + 2];
         q3 = c.yl[s + 3];
-        cyc_step<H>(s, c, x, A, Bv, up_in, diag_in, raw_up, raw_diag, q0, q1, q2, q3, xp, yp, n, m, b,
-                    Qf);
+        cyc_step<H, RB>(s, c, x, A, Bv, up_in, diag_in, raw_up, raw_diag, q0, q1, q2, q3, xp, yp, n, m, b, Qf);
     }
     if (rem >= 2)
-        cyc_step<H>(s + 1, c, x, Bv, A, up_in, diag_in, raw_up, raw_diag, q1, q2, q3, q0, xp, yp, n, m,
+        cyc_step<H, RB>(s + 1, c, x, Bv, A, up_in, diag_in, raw_up, raw_diag, q1, q2, q3, q0, xp, yp, n, m,
                     b, Qf);
     if (rem >= 3)
-        cyc_step<H>(s + 2, c, x, A, Bv, up_in, diag_in, raw_up, raw_diag, q2, q3, q0, q1, xp, yp, n, m,
+        cyc_step<H, RB>(s + 2, c, x, A, Bv, up_in, diag_in, raw_up, raw_diag, q2, q3, q0, q1, xp, yp, n, m,
                     b, Qf);
     const float res = (rem & 1) ? Bv[hf] : A[hf];
-    if (lane == (Qf & 63)) DI.out[it.slot] = res;
+    if (lane == (Qf & 63)) DI.out[it.slot] = RB ? res + base : res;
 }
 
-// Waves per SIMD the register allocation aims for: H = 28 fits 4 (126 VGPRs,
-// no scratch) instead of 3 when asked; H = 20, 24 and 32 would spill.
-template <int H>
-constexpr int cyc_min_waves() { return H == 28 ? 4 : 1; }
+// Waves per SIMD the register allocation aims for: plain H = 28 fits 4 (126
+// VGPRs, no scratch) instead of 3 when asked; H = 20, 24 and 32, and the
+// rebased H = 28 (two more registers), would spill.
+template <int H, bool RB>
+constexpr int cyc_min_waves() { return H == 28 && !RB ? 4 : 1; }
 
-template <int H>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(cyc_min_waves<H>()))) void k_strip_cyc(const float *__restrict__ ws, const SeriesInfo *__restrict__ ser,
+template <int H, bool RB>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(cyc_min_waves<H, RB>()))) void k_strip_cyc(const float *__restrict__ ws, const SeriesInfo *__restrict__ ser,
                                                   const DatasetInfo *__restrict__ dsi,
                                                   const WaveItem *__restrict__ items, unsigned *__restrict__ queue,
                                                   unsigned n_items) {
@@ -238,25 +278,29 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(cyc_min_wave
     for (;;) {
         if (queue) idx = next_item<1>(queue, nullptr);
         if (idx >= n_items) break;
-        cyc_item<H>(items[idx], ws, ser, dsi);
+        cyc_item<H, RB>(items[idx], ws, ser, dsi);
         if (!queue) break;
     }
 }
 
 template <int H>
-hipError_t cyc_launch(const float *ws, const SeriesInfo *ser, const DatasetInfo *dsi, const WaveItem *items,
+hipError_t cyc_launch(bool rb, const float *ws, const SeriesInfo *ser, const DatasetInfo *dsi, const WaveItem *items,
                       unsigned n, unsigned *queue, unsigned grid, hipStream_t st) {
-    hipLaunchKernelGGL((k_strip_cyc<H>), dim3(grid), dim3(64), 0, st, ws, ser, dsi, items, queue, n);
+    if (rb)
+        hipLaunchKernelGGL((k_strip_cyc<H, true>), dim3(grid), dim3(64), 0, st, ws, ser, dsi, items, queue, n);
+    else
+        hipLaunchKernelGGL((k_strip_cyc<H, false>), dim3(grid), dim3(64), 0, st, ws, ser, dsi, items, queue, n);
     return hipGetLastError();
 }
 
 template <int H>
-int cyc_slots() {
-    return resident_blocks(reinterpret_cast<const void *>(&k_strip_cyc<H>), 64);
+int cyc_slots(bool rb) {
+    return rb ? resident_blocks(reinterpret_cast<const void *>(&k_strip_cyc<H, true>), 64)
+              : resident_blocks(reinterpret_cast<const void *>(&k_strip_cyc<H, false>), 64);
 }
 
-using SlotsFn = int (*)();
-using CycFn = hipError_t (*)(const float *, const SeriesInfo *, const DatasetInfo *, const WaveItem *, unsigned,
+using SlotsFn = int (*)(bool);
+using CycFn = hipError_t (*)(bool, const float *, const SeriesInfo *, const DatasetInfo *, const WaveItem *, unsigned,
                              unsigned *, unsigned, hipStream_t);
 struct CycEntry {
     int H;
@@ -287,17 +331,18 @@ int cyclic_shapes(int *H_out, int max_out) {
     return k;
 }
 
-int cyclic_resident(int H) {
+int cyclic_resident(int H, bool rebased) {
     for (const CycEntry &e : kCyclic)
-        if (e.H == H) return e.slots();
+        if (e.H == H) return e.slots(rebased);
     return 0;
 }
 
-hipError_t launch_cyclic(int H, const float *ws, const SeriesInfo *ser, const DatasetInfo *dsi,
+hipError_t launch_cyclic(int H, bool rebased, const float *ws, const SeriesInfo *ser, const DatasetInfo *dsi,
                          const WaveItem *items, unsigned n_items, unsigned *queue, int slots, hipStream_t stream) {
     if (n_items == 0) return hipSuccess;
     for (const CycEntry &e : kCyclic)
-        if (e.H == H) return e.fn(ws, ser, dsi, items, n_items, queue, grid_for(n_items, queue, slots), stream);
+        if (e.H == H)
+            return e.fn(rebased, ws, ser, dsi, items, n_items, queue, grid_for(n_items, queue, slots), stream);
     return hipErrorInvalidValue;
 }
 

@@ -20,6 +20,8 @@
 
 #include "dtw_internal.h"
 
+#include <type_traits>
+
 namespace dtwmi {
 namespace {
 
@@ -41,6 +43,26 @@ __device__ __forceinline__ double lane_shift_down(double v, double fill) {
     const int lo = __builtin_amdgcn_update_dpp((int)(fb & 0xffffffff), (int)(vb & 0xffffffff), 0x138, 0xF, 0xF, false);
     const int hi = __builtin_amdgcn_update_dpp((int)(fb >> 32), (int)(vb >> 32), 0x138, 0xF, 0xF, false);
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Minimum of v over the 64 lanes of the wavefront, returned to every lane:
+// butterflies within each row of 16 lanes by DPP (quad swaps, then rotations
+// by 4 and 8), then the four row minima read from lanes 0, 16, 32 and 48.
+// Every lane must be active.
+__device__ __forceinline__ float wave_min(float v) {
+    auto dpp = [](float a, auto ctrl) {
+        return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(a), decltype(ctrl)::value, 0xF, 0xF, true));
+    };
+    v = fminf(v, dpp(v, std::integral_constant<int, 0xB1>{}));   // quad_perm [1,0,3,2]
+    v = fminf(v, dpp(v, std::integral_constant<int, 0x4E>{}));   // quad_perm [2,3,0,1]
+    v = fminf(v, dpp(v, std::integral_constant<int, 0x124>{}));  // row_ror:4
+    v = fminf(v, dpp(v, std::integral_constant<int, 0x128>{}));  // row_ror:8
+    const int b = __float_as_int(v);
+    const float r0 = __int_as_float(__builtin_amdgcn_readlane(b, 0));
+    const float r1 = __int_as_float(__builtin_amdgcn_readlane(b, 16));
+    const float r2 = __int_as_float(__builtin_amdgcn_readlane(b, 32));
+    const float r3 = __int_as_float(__builtin_amdgcn_readlane(b, 48));
+    return fminf(fminf(r0, r1), fminf(r2, r3));
 }
 
 __device__ __forceinline__ int64_t condensed_index(int i, int j, int N) {

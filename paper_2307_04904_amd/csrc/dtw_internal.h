@@ -16,6 +16,16 @@ namespace dtwmi {
 constexpr int kPad = 128;
 constexpr int kLaneMaxW = 127;   // widest band (2*B+1) of the lane-band kernel
 
+// Accumulation of a kernel instance (the public dtw_accum AUTO resolves to
+// kAccPlain or kAccRebased per pair):
+//   kAccPlain:   FP32 sub, min3, fused multiply-add per cell;
+//   kAccKahan:   FP32 with a compensation term carried per cell;
+//   kAccF64:     the recurrence in FP64, rounded once at the end;
+//   kAccRebased: the plain FP32 cell, every lane keeping its values relative
+//                to a running base of its own that it renormalises every few
+//                steps (rounding relative to the small stored values).
+enum AccMode { kAccPlain = 0, kAccKahan = 1, kAccF64 = 2, kAccRebased = 3 };
+
 
 struct SeriesSrc {     // where a series lives in the caller's buffer
     const void *base;  // device pointer of the dataset buffer
@@ -69,31 +79,35 @@ struct WaveItem {
 hipError_t launch_stage(const SeriesSrc *src, const SeriesInfo *ser, float *ws, int32_t nseries,
                         hipStream_t stream);
 hipError_t launch_zero(unsigned *p, int n, hipStream_t stream);
+// Set every SeriesSrc.base of a one-dataset plan to `series` and its output to `out`.
+hipError_t launch_rebind(SeriesSrc *src, int32_t nseries, const void *series, DatasetInfo *dsi, float *out,
+                         hipStream_t stream);
 // Workgroups of `block` threads of kernel `fn` the current device holds at
 // once (CUs x occupancy per CU; 0 if it cannot be queried).
 int resident_blocks(const void *fn, int block);
 bool lane_width_supported(int W);
 // Lane-band items all cost the same: one workgroup per item, no queue.
-hipError_t launch_lane(int W, const float *ws, const SeriesInfo *ser, const DatasetInfo *dsi,
+// rebased: kAccRebased sums instead of kAccPlain.
+hipError_t launch_lane(int W, bool rebased, const float *ws, const SeriesInfo *ser, const DatasetInfo *dsi,
                        const LaneItem *items, const LanePartner *partners, unsigned n_items, hipStream_t stream);
 // Strip shapes of the wavefront kernels: H rows per lane, G wavefronts per pair
 // (a workgroup of 64*G lanes covers up to 64*H*G rows of the shorter series).
 struct StripShape {
     int H, G;
 };
-// Instantiated shapes for an accumulation mode, in increasing row capacity;
+// Instantiated shapes for an accumulation mode (AccMode), in increasing row capacity;
 // returns their number (writes at most max_out of them).
 int strip_shapes(int accum, StripShape *out, int max_out);
 int strip_resident(int accum, StripShape shape, bool banded);
 hipError_t launch_strip(int accum, StripShape shape, bool banded, const float *ws, const SeriesInfo *ser,
                         const DatasetInfo *dsi, const WaveItem *items, unsigned n_items, unsigned *queue, int slots,
                         hipStream_t stream);
-// Cyclic banded strips (PLAIN, window required): H rows per block, blocks
-// cycling over the 64 lanes of one wavefront; needs 64(H+1) >= 2b+H whenever
-// the pair has more than 64 blocks.
+// Cyclic banded strips (kAccPlain or, with rebased, kAccRebased; window
+// required): H rows per block, blocks cycling over the 64 lanes of one
+// wavefront; needs 64(H+1) >= 2b+H whenever the pair has more than 64 blocks.
 int cyclic_shapes(int *H_out, int max_out);
-int cyclic_resident(int H);
-hipError_t launch_cyclic(int H, const float *ws, const SeriesInfo *ser, const DatasetInfo *dsi,
+int cyclic_resident(int H, bool rebased);
+hipError_t launch_cyclic(int H, bool rebased, const float *ws, const SeriesInfo *ser, const DatasetInfo *dsi,
                          const WaveItem *items, unsigned n_items, unsigned *queue, int slots, hipStream_t stream);
 
 // Last-error message of the calling thread (dtw_last_error), for every host

@@ -1,185 +1,25 @@
-// HIP kernels (gfx950) for the all-pairs DTW distance matrix.
-//
-// Every kernel evaluates the recurrence of Eq. (c) of the paper
-// ("Mathematical background"):
-//     c(i,j) = (x_i - y_j)^2 + min{ c(i-1,j-1), c(i-1,j), c(i,j-1) }
-// keeping only O(row) state in registers -- the GPU form of the paper's
-// "preceding vector" scheme -- and writes c(n,m) into the condensed distance
-// matrix D (same section).  The window rule |i-j| <= max(w,|n-m|) follows the
-// paper's Introduction.  The recurrence is a min-plus scan, so all work is
-// FP32 (or FP64) VALU: v_sub, v_min3, v_fma per cell; no matrix cores.
-//
-// This file: the lane-band kernel (one pair per lane, equal lengths, narrow
-// band), used for datasets of equal-length series.
-#include "dtw_device.h"
-
-#include <array>
-#include <utility>
+// Lane-band kernel instances with plain FP32 sums (the kernel: dtw_lane.h).
+#include "dtw_lane.h"
 
 namespace dtwmi {
 namespace {
 
-// ---------------------------------------------------------------------------
-// Lane-band kernel.
-//
-// Row i of the band holds cells k = 0..W-1 (column i-B+k), updated in place:
-//   new[k] = (x_i - y_{i-B+k})^2 + min3(old[k], old[k+1], new[k-1]).
-// R consecutive rows are swept together, row i+r lagging 2 cells behind row
-// i+r-1: at step t row i+r updates cell t-2r, which only reads cells row
-// i+r-1 finished at steps t-2 and t-1, so the R updates of a step are
-// independent (R chains of instruction-level parallelism per lane) and all
-// still happen in place.  Step t of row i+r uses y[i-B+t-r]: a window of
-// C+R-1 wave-uniform values per chunk of C steps, fetched into SGPRs with
-// scalar loads one chunk ahead; a scheduling barrier keeps the compiler from
-// hoisting the loads of a whole row (which would exceed the SGPR file).
-// A chunk whose columns all lie outside [0, L) is skipped with a wave-uniform
-// branch: cells left of column 0 are +inf and stay +inf, and cells right of
-// column L-1 are never read by an admissible cell.
-#ifndef DTWMI_LANE_ROWS
-#define DTWMI_LANE_ROWS 4
-#endif
-#ifndef DTWMI_LANE_CHUNK
-#define DTWMI_LANE_CHUNK 16
-#endif
-constexpr int kLaneRows = DTWMI_LANE_ROWS;
-constexpr int kLaneChunk = DTWMI_LANE_CHUNK;
-
-template <int W>
-__device__ __forceinline__ void lane_cell(float (&st)[W], int k, float xi, float yk) {
-    const float d = xi - yk;
-    float t;
-    if (W == 1) {
-        t = st[0];
-    } else if (k == 0) {
-        t = fminf(st[0], st[1]);  // left of the band is +inf
-    } else if (k == W - 1) {
-        t = fminf(st[W - 1], st[W - 2]);  // up is outside the band
-    } else {
-        t = min3f(st[k], st[k + 1], st[k - 1]);
-    }
-    st[k] = fmaf(d, d, t);
-}
-
-// One chunk (steps CH*C .. CH*C+C-1) of a group of R rows starting at row i,
-// then the following chunks.  ybase[v] = y[i-B-(R-1)+v]; ycur holds this
-// chunk's window on entry and the first window of the next group (read from
-// ynext) on exit.  col0 = i-B is the column of cell 0 of row i.
-template <int W, int R, int C, int CH>
-__device__ __forceinline__ void lane_group(float (&st)[W], const float (&x)[R], const float *__restrict__ ybase,
-                                           const float *__restrict__ ynext, float (&ycur)[C + R - 1], int col0,
-                                           int L) {
-    constexpr int T = W + 2 * (R - 1), NY = C + R - 1, NCH = (T + C - 1) / C, T0 = CH * C;
-    float ynxt[NY];
-#pragma unroll
-    for (int u = 0; u < NY; ++u) ynxt[u] = (CH + 1 < NCH) ? ybase[T0 + C + u] : ynext[u];
-    __builtin_amdgcn_sched_barrier(0);
-    const bool live = (col0 + T0 + C - 1 >= 0) && (col0 + T0 - (R - 1) < L);
-    if (live) {
-#pragma unroll
-        for (int u = 0; u < C; ++u) {
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const int p = T0 + u - 2 * r;
-                if (p >= 0 && p < W) lane_cell<W>(st, p, x[r], ycur[u + R - 1 - r]);
-            }
-        }
-    }
-#pragma unroll
-    for (int u = 0; u < NY; ++u) ycur[u] = ynxt[u];
-    if constexpr (CH + 1 < NCH) lane_group<W, R, C, CH + 1>(st, x, ybase, ynext, ycur, col0, L);
-}
-
-// Lane-band items have equal cost, so the kernel takes one item per workgroup
-// (hardware dispatch); an item loop would only add registers to this kernel.
-template <int W>
-__global__ __launch_bounds__(64) void k_lane(const float *__restrict__ ws, const SeriesInfo *__restrict__ ser,
-                                             const DatasetInfo *__restrict__ dsi,
-                                             const LaneItem *__restrict__ items,
-                                             const LanePartner *__restrict__ partners) {
-    constexpr int B = (W - 1) / 2, R = kLaneRows, C = kLaneChunk;
-    const LaneItem it = items[blockIdx.x];
-    const DatasetInfo D = dsi[it.ds];
-    const int lane = threadIdx.x;
-    const bool valid = lane < it.cnt;
-    int bl;
-    int64_t slot;
-    if (it.list < 0) {  // all pairs: cyclic partner tiling, condensed output
-        bl = it.a + it.d0 + lane;
-        bl = bl >= D.N ? bl - D.N : bl;
-        const int a = it.a < bl ? it.a : bl, b = it.a < bl ? bl : it.a;
-        slot = condensed_index(a, b, D.N);
-    } else {  // explicit pair list
-        const LanePartner P = partners[it.list + (valid ? lane : 0)];
-        bl = P.b;
-        slot = P.slot;
-    }
-    if (!valid) bl = it.a;  // idle lanes recompute a valid pair and store nothing
-    const float *__restrict__ ycol = ws + ser[D.series_base + it.a].pstart - B;  // ycol[v] = y[v-B]
-    const float *__restrict__ xrow = ws + ser[D.series_base + bl].pstart;
-    const int L = D.L;
-
-    float st[W];
-#pragma unroll
-    for (int k = 0; k < W; ++k) st[k] = kInf;
-    st[B] = 0.0f;  // c(0,0) of the 1-based recurrence, seen as the diagonal of cell (1,1)
-
-    int i = 0;
-    if (L >= R) {
-        float ycur[C + R - 1];
-#pragma unroll
-        for (int u = 0; u < C + R - 1; ++u) ycur[u] = ycol[u - (R - 1)];
-        float x[R];
-#pragma unroll
-        for (int r = 0; r < R; ++r) x[r] = xrow[r];
-        for (; i + R <= L; i += R) {
-            float xn[R];  // next group's x, requested one group ahead (stays inside the pad)
-#pragma unroll
-            for (int r = 0; r < R; ++r) xn[r] = xrow[i + R + r];
-            lane_group<W, R, C, 0>(st, x, ycol + i - (R - 1), ycol + i + 1, ycur, i - B, L);
-#pragma unroll
-            for (int r = 0; r < R; ++r) x[r] = xn[r];
-        }
-    }
-    if constexpr (R > 1) {
-        for (; i < L; ++i) {  // rows left over when R does not divide L
-            float ycur[C];
-#pragma unroll
-            for (int u = 0; u < C; ++u) ycur[u] = ycol[i + u];
-            const float x1[1] = {xrow[i]};
-            lane_group<W, 1, C, 0>(st, x1, ycol + i, ycol + i + 1, ycur, i - B, L);
-        }
-    }
-
-    if (valid) D.out[slot] = st[B];
-}
-
-
-using LaneFn = hipError_t (*)(const float *, const SeriesInfo *, const DatasetInfo *, const LaneItem *,
-                              const LanePartner *, unsigned, hipStream_t);
-
-template <int I>
-hipError_t lane_launcher(const float *ws, const SeriesInfo *ser, const DatasetInfo *dsi, const LaneItem *items,
-                         const LanePartner *partners, unsigned n, hipStream_t st) {
-    hipLaunchKernelGGL(k_lane<2 * I + 1>, dim3(n), dim3(64), 0, st, ws, ser, dsi, items, partners);
-    return hipGetLastError();
-}
-
-template <size_t... I>
-constexpr std::array<LaneFn, sizeof...(I)> make_lane_table(std::index_sequence<I...>) {
-    return {{&lane_launcher<static_cast<int>(I)>...}};
-}
-
 const std::array<LaneFn, (kLaneMaxW + 1) / 2> kLaneTable =
-    make_lane_table(std::make_index_sequence<(kLaneMaxW + 1) / 2>{});
+    make_lane_table<false>(std::make_index_sequence<(kLaneMaxW + 1) / 2>{});
 
 }  // namespace
 
 bool lane_width_supported(int W) { return W >= 1 && W <= kLaneMaxW && (W & 1); }
 
-hipError_t launch_lane(int W, const float *ws, const SeriesInfo *ser, const DatasetInfo *dsi,
+hipError_t launch_lane_rebased(int W, const float *ws, const SeriesInfo *ser, const DatasetInfo *dsi,
+                               const LaneItem *items, const LanePartner *partners, unsigned n_items,
+                               hipStream_t stream);
+
+hipError_t launch_lane(int W, bool rebased, const float *ws, const SeriesInfo *ser, const DatasetInfo *dsi,
                        const LaneItem *items, const LanePartner *partners, unsigned n_items, hipStream_t stream) {
     if (!lane_width_supported(W)) return hipErrorInvalidValue;
     if (n_items == 0) return hipSuccess;
+    if (rebased) return launch_lane_rebased(W, ws, ser, dsi, items, partners, n_items, stream);
     return kLaneTable[(W - 1) / 2](ws, ser, dsi, items, partners, n_items, stream);
 }
 

@@ -37,6 +37,15 @@ __global__ __launch_bounds__(64) void k_zero(unsigned *__restrict__ p, int n) {
     for (int i = threadIdx.x; i < n; i += 64) p[i] = 0u;
 }
 
+// Re-point a one-dataset plan at other buffers of the same shape: every
+// series' source buffer and the dataset's output.
+__global__ __launch_bounds__(256) void k_rebind(SeriesSrc *__restrict__ src, int nseries, const void *series,
+                                                DatasetInfo *__restrict__ dsi, float *out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nseries) src[i].base = series;
+    if (i == 0) dsi[0].out = out;
+}
+
 }  // namespace
 
 int resident_blocks(const void *fn, int block) {
@@ -51,6 +60,13 @@ hipError_t launch_stage(const SeriesSrc *src, const SeriesInfo *ser, float *ws, 
                         hipStream_t stream) {
     if (nseries <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_stage, dim3(nseries), dim3(256), 0, stream, src, ser, ws);
+    return hipGetLastError();
+}
+
+hipError_t launch_rebind(SeriesSrc *src, int32_t nseries, const void *series, DatasetInfo *dsi, float *out,
+                         hipStream_t stream) {
+    hipLaunchKernelGGL(k_rebind, dim3((nseries + 255) / 256 > 0 ? (nseries + 255) / 256 : 1), dim3(256), 0, stream,
+                       src, nseries, series, dsi, out);
     return hipGetLastError();
 }
 

@@ -36,6 +36,48 @@ struct AccPlain {  // FP32: sub, min3, fused multiply-add
     __device__ static float result(T v) { return v; }
 };
 
+// Rebased FP32: the cells of AccPlain, with the values of a wavefront stored
+// relative to a base it shares (true value = stored value + base).  Every few
+// steps the base moves up to the smallest value on the wavefront's current
+// frontier -- its lanes' current cells, the boundary values they hold and,
+// for a wavefront after the first, every value of the LDS ring from the
+// wavefront above and the base that one last posted.  Every path to a cell
+// computed later passes through that frontier and local costs are never
+// negative, so the base stays below every value computed afterwards: stored
+// values lie between 0 and the true cost, and each fused add rounds relative
+// to the stored value -- the distance of the path above the frontier's
+// cheapest cell plus what it gained since the last renormalisation -- instead
+// of the whole cumulative cost.  The rounding is never larger than that of
+// plain sums and on long paths typically an order of magnitude smaller.
+// Values between lanes need no conversion (one base); values handed between
+// wavefronts through LDS travel as absolute values.
+struct AccRebased : AccPlain {};
+
+template <class ACC>
+constexpr bool kRebased = std::is_same<ACC, AccRebased>::value;
+
+// Steps between renormalisations (one-column and two-column sweeps).
+constexpr int kRebaseSteps = 32;
+constexpr int kRebaseSteps2 = 16;
+
+// Renormalise a wavefront: the base moves up by the smallest of the H cells of
+// every lane and `held` (the lane's other frontier values, relative to the
+// base); returns the shift applied (the difference of the new and the old base
+// as computed, subtracted from every stored value).  All +inf: no shift.
+template <int H>
+__device__ __forceinline__ float rebase_wave(float (&A)[H], float held, float &base) {
+    float mn = held;
+#pragma unroll
+    for (int h = 0; h < H; ++h) mn = fminf(mn, A[h]);
+    mn = wave_min(mn);
+    const float nb = base + (mn < kInf ? mn : 0.0f);
+    const float d = nb - base;
+#pragma unroll
+    for (int h = 0; h < H; ++h) A[h] -= d;
+    base = nb;
+    return d;
+}
+
 // Kahan-compensated FP32: each cell carries (s, c) with the true value close
 // to s - c.  The min compares the running sums s (ties prefer diag, then up,
 // then left) and takes the compensation of the chosen predecessor; the local
@@ -151,7 +193,7 @@ __device__ __forceinline__ void strip_step(int c, float yv, const XT &x, const t
 template <class ACC, int H, int G, bool BANDED>
 __device__ __forceinline__ void strip_item(const WaveItem it, const float *__restrict__ ws,
                                            const SeriesInfo *__restrict__ ser, const DatasetInfo *__restrict__ dsi,
-                                           typename ACC::T (*ring)[kRing]) {
+                                           typename ACC::T (*ring)[kRing], float *bound) {
     using T = typename ACC::T;
     constexpr bool EVENTS = BANDED && H <= 32;  // wider strips test every cell
     constexpr bool PERCELL = BANDED && !EVENTS;
@@ -192,10 +234,14 @@ __device__ __forceinline__ void strip_item(const WaveItem it, const float *__res
     if constexpr (EVENTS) ev.init(rbase, skew, band);
     if constexpr (G > 1) {
         for (int k = threadIdx.x; k < (G - 1) * kRing; k += 64 * G) ring[k / kRing][k % kRing] = ACC::inf();
+        if constexpr (kRebased<ACC>) {
+            if (threadIdx.x < G) bound[threadIdx.x] = 0.0f;  // the trivial lower bound
+        }
         __syncthreads();
     }
     T up_in = ACC::inf();
     T diag_in = (lane == 0 && wave == 0) ? ACC::zero() : ACC::inf();  // c(0,0) of the 1-based recurrence
+    float base = 0.0f;  // rebased accumulation only: the wavefront's base
 
     // y of column s - skew; the +inf pads cover the columns a single wavefront
     // reads ([-63, m+64]), later wavefronts clamp into [-1, m]
@@ -207,13 +253,21 @@ __device__ __forceinline__ void strip_item(const WaveItem it, const float *__res
     // value handed to lane 0 of this wavefront (LDS ring for wavefronts after the first)
     auto boundary = [&](int s) -> T {
         if constexpr (G > 1) {
-            if (wave > 0) return ring[wave - 1][(s - skew) & (kRing - 1)];
+            if (wave > 0) {
+                if constexpr (kRebased<ACC>) return ring[wave - 1][(s - skew) & (kRing - 1)] - base;
+                return ring[wave - 1][(s - skew) & (kRing - 1)];
+            }
         }
         return ACC::inf();
     };
     auto publish = [&](int s, const T &bottom) {
         if constexpr (G > 1) {
-            if (lane == 63 && wave < G - 1) ring[wave][(s - skew) & (kRing - 1)] = bottom;
+            if (lane == 63 && wave < G - 1) {
+                if constexpr (kRebased<ACC>)
+                    ring[wave][(s - skew) & (kRing - 1)] = bottom + base;
+                else
+                    ring[wave][(s - skew) & (kRing - 1)] = bottom;
+            }
         }
     };
 
@@ -239,6 +293,20 @@ __device__ __forceinline__ void strip_item(const WaveItem it, const float *__res
             diag_in = up_in;
             up_in = recv;
         }
+        if constexpr (kRebased<ACC>) {
+            if ((s + 2) % kRebaseSteps == 0) {
+                float held = fminf(up_in, diag_in);
+                if constexpr (G > 1) {
+                    if (wave > 0) held = fminf(held, fminf(ring[wave - 1][lane], bound[wave - 1]) - base);
+                }
+                const float d = rebase_wave<H>(A, held, base);
+                up_in -= d;
+                diag_in -= d;
+                if constexpr (G > 1) {
+                    if (lane == 0) bound[wave] = base;
+                }
+            }
+        }
         y0 = y2;
         y1 = y3;
         if constexpr (G > 1) {
@@ -253,7 +321,12 @@ __device__ __forceinline__ void strip_item(const WaveItem it, const float *__res
     } else {
         res = pick<H>(A, hf);
     }
-    if (wave == wf && lane == lf) DI.out[it.slot] = ACC::result(res);
+    if (wave == wf && lane == lf) {
+        if constexpr (kRebased<ACC>)
+            DI.out[it.slot] = res + base;
+        else
+            DI.out[it.slot] = ACC::result(res);
+    }
 }
 
 // Unwindowed strips, two columns per step.  Lane l of wavefront g handles
@@ -268,7 +341,7 @@ __device__ __forceinline__ void strip_item(const WaveItem it, const float *__res
 template <class ACC, int H, int G>
 __device__ __forceinline__ void strip2_item(const WaveItem it, const float *__restrict__ ws,
                                             const SeriesInfo *__restrict__ ser, const DatasetInfo *__restrict__ dsi,
-                                            typename ACC::T (*ring)[kRing]) {
+                                            typename ACC::T (*ring)[kRing], float *bound) {
     using T = typename ACC::T;
     constexpr int D = G > 1 ? kEpoch : 0;
 
@@ -297,6 +370,9 @@ __device__ __forceinline__ void strip2_item(const WaveItem it, const float *__re
     }
     if constexpr (G > 1) {
         for (int k = threadIdx.x; k < (G - 1) * kRing; k += 64 * G) ring[k / kRing][k % kRing] = ACC::inf();
+        if constexpr (kRebased<ACC>) {
+            if (threadIdx.x < G) bound[threadIdx.x] = 0.0f;  // the trivial lower bound
+        }
         __syncthreads();
     }
     // Row -1 as seen by lane 0 of wavefront 0: +inf, except c(0,0) = 0 of the
@@ -305,6 +381,7 @@ __device__ __forceinline__ void strip2_item(const WaveItem it, const float *__re
     T recv0 = (corner && shift) ? ACC::zero() : ACC::inf();   // bottom of column c0 from the lane above
     T recv1 = ACC::inf();                                     // bottom of column c0 + 1
     T prev1 = (corner && !shift) ? ACC::zero() : ACC::inf();  // bottom of column c0 - 1
+    float base = 0.0f;  // rebased accumulation only: the wavefront's base
 
     auto col_of = [&](int t) { return 2 * (t - skew) - shift; };  // first column of step t
     // y of column c: a single wavefront reads columns [-127, m+127] (inside
@@ -315,7 +392,10 @@ __device__ __forceinline__ void strip2_item(const WaveItem it, const float *__re
     };
     auto boundary = [&](int t, int k) -> T {  // lane 0's up value for column k of step t
         if constexpr (G > 1) {
-            if (wave > 0) return ring[wave - 1][(col_of(t) + k) & (kRing - 1)];
+            if (wave > 0) {
+                if constexpr (kRebased<ACC>) return ring[wave - 1][(col_of(t) + k) & (kRing - 1)] - base;
+                return ring[wave - 1][(col_of(t) + k) & (kRing - 1)];
+            }
         }
         return ACC::inf();
     };
@@ -323,8 +403,13 @@ __device__ __forceinline__ void strip2_item(const WaveItem it, const float *__re
         if constexpr (G > 1) {
             if (lane == 63 && wave < G - 1) {
                 const int c = col_of(t);
-                ring[wave][c & (kRing - 1)] = b0;
-                ring[wave][(c + 1) & (kRing - 1)] = b1;
+                if constexpr (kRebased<ACC>) {
+                    ring[wave][c & (kRing - 1)] = b0 + base;
+                    ring[wave][(c + 1) & (kRing - 1)] = b1 + base;
+                } else {
+                    ring[wave][c & (kRing - 1)] = b0;
+                    ring[wave][(c + 1) & (kRing - 1)] = b1;
+                }
             }
         }
     };
@@ -354,13 +439,33 @@ __device__ __forceinline__ void strip2_item(const WaveItem it, const float *__re
         prev1 = recv1;
         recv0 = lane_shift_down(bm1, boundary(t + 1, 0));
         recv1 = lane_shift_down(A[H - 1], boundary(t + 1, 1));
+        if constexpr (kRebased<ACC>) {
+            if ((t + 1) % kRebaseSteps2 == 0) {
+                float held = fminf(fminf(recv0, recv1), prev1);
+                if constexpr (G > 1) {
+                    if (wave > 0) held = fminf(held, fminf(ring[wave - 1][lane], bound[wave - 1]) - base);
+                }
+                const float d = rebase_wave<H>(A, held, base);
+                recv0 -= d;
+                recv1 -= d;
+                prev1 -= d;
+                if constexpr (G > 1) {
+                    if (lane == 0) bound[wave] = base;
+                }
+            }
+        }
         y0 = n0;
         y1 = n1;
         if constexpr (G > 1) {
             if ((t + 1) % kEpoch == 0) __syncthreads();
         }
     }
-    if (wave == wf && lane == lf) DI.out[it.slot] = ACC::result(pick<H>(A, hf));
+    if (wave == wf && lane == lf) {
+        if constexpr (kRebased<ACC>)
+            DI.out[it.slot] = pick<H>(A, hf) + base;
+        else
+            DI.out[it.slot] = ACC::result(pick<H>(A, hf));
+    }
 }
 
 template <class ACC, int H, int G, bool BANDED>
@@ -369,6 +474,7 @@ __global__ __launch_bounds__(64 * G) void k_strip(const float *__restrict__ ws, 
                                                   const WaveItem *__restrict__ items, unsigned *__restrict__ queue,
                                                   unsigned n_items) {
     __shared__ typename ACC::T ring[G > 1 ? G - 1 : 1][kRing];
+    __shared__ float bound[G];  // rebased multi-wavefront strips: each wavefront's last base
     __shared__ unsigned slot;
     unsigned idx = blockIdx.x;
     for (;;) {
@@ -377,10 +483,10 @@ __global__ __launch_bounds__(64 * G) void k_strip(const float *__restrict__ ws, 
         // unwindowed plain FP32 strips take two columns per step; the
         // compensated and FP64 cells already hold enough independent work
         // per cell (measured slower in the two-column form)
-        if constexpr (!BANDED && std::is_same<ACC, AccPlain>::value)
-            strip2_item<ACC, H, G>(items[idx], ws, ser, dsi, ring);
+        if constexpr (!BANDED && (std::is_same<ACC, AccPlain>::value || kRebased<ACC>))
+            strip2_item<ACC, H, G>(items[idx], ws, ser, dsi, ring, bound);
         else
-            strip_item<ACC, H, G, BANDED>(items[idx], ws, ser, dsi, ring);
+            strip_item<ACC, H, G, BANDED>(items[idx], ws, ser, dsi, ring, bound);
         if (!queue) break;
     }
 }
@@ -425,6 +531,16 @@ const StripEntry kStrips[] = {
     DTWMI_STRIP(0, AccPlain, 48, 1), DTWMI_STRIP(0, AccPlain, 24, 2), DTWMI_STRIP(0, AccPlain, 56, 1),
     DTWMI_STRIP(0, AccPlain, 64, 1), DTWMI_STRIP(0, AccPlain, 32, 2), DTWMI_STRIP(0, AccPlain, 32, 4),
     DTWMI_STRIP(0, AccPlain, 32, 8), DTWMI_STRIP(0, AccPlain, 64, 8),
+    // rebased FP32: the same shapes
+    DTWMI_STRIP(3, AccRebased, 1, 1),  DTWMI_STRIP(3, AccRebased, 2, 1),  DTWMI_STRIP(3, AccRebased, 3, 1),
+    DTWMI_STRIP(3, AccRebased, 4, 1),  DTWMI_STRIP(3, AccRebased, 5, 1),  DTWMI_STRIP(3, AccRebased, 6, 1),
+    DTWMI_STRIP(3, AccRebased, 7, 1),  DTWMI_STRIP(3, AccRebased, 8, 1),  DTWMI_STRIP(3, AccRebased, 10, 1),
+    DTWMI_STRIP(3, AccRebased, 12, 1), DTWMI_STRIP(3, AccRebased, 14, 1), DTWMI_STRIP(3, AccRebased, 16, 1),
+    DTWMI_STRIP(3, AccRebased, 20, 1), DTWMI_STRIP(3, AccRebased, 24, 1), DTWMI_STRIP(3, AccRebased, 28, 1),
+    DTWMI_STRIP(3, AccRebased, 32, 1), DTWMI_STRIP(3, AccRebased, 16, 2), DTWMI_STRIP(3, AccRebased, 40, 1),
+    DTWMI_STRIP(3, AccRebased, 48, 1), DTWMI_STRIP(3, AccRebased, 24, 2), DTWMI_STRIP(3, AccRebased, 56, 1),
+    DTWMI_STRIP(3, AccRebased, 64, 1), DTWMI_STRIP(3, AccRebased, 32, 2), DTWMI_STRIP(3, AccRebased, 32, 4),
+    DTWMI_STRIP(3, AccRebased, 32, 8), DTWMI_STRIP(3, AccRebased, 64, 8),
     DTWMI_STRIP(1, AccKahan, 1, 1),  DTWMI_STRIP(1, AccKahan, 2, 1),  DTWMI_STRIP(1, AccKahan, 4, 1),
     DTWMI_STRIP(1, AccKahan, 8, 1),  DTWMI_STRIP(1, AccKahan, 16, 1), DTWMI_STRIP(1, AccKahan, 16, 2),
     DTWMI_STRIP(1, AccKahan, 16, 4), DTWMI_STRIP(1, AccKahan, 16, 8), DTWMI_STRIP(1, AccKahan, 16, 16),

@@ -50,7 +50,8 @@ def test_band_cells_sweep():
         assert B.dtw_band_cells(n, m, w) == oracle.band_cells(n, m, w)
 
 
-def _call_ex(lengths, offsets, N=None, window=-1, series=FAKE_DEV, out=FAKE_DEV, dtype=0, accum=0, kernel=0, flags=0):
+def _call_ex(lengths, offsets, N=None, window=-1, series=FAKE_DEV, out=FAKE_DEV, dtype=0, accum=0, kernel=0, flags=0,
+             k_range=(0, 0)):
     lib = B.load()
     ln = np.ascontiguousarray(lengths, dtype=np.int32)
     off = np.ascontiguousarray(offsets, dtype=np.int64)
@@ -63,6 +64,7 @@ def _call_ex(lengths, offsets, N=None, window=-1, series=FAKE_DEV, out=FAKE_DEV,
     d.out_condensed = ctypes.c_void_p(out)
     o = B.dtw_options()
     o.dtype, o.accum, o.kernel, o.flags = dtype, accum, kernel, flags
+    o.k_begin, o.k_end = k_range
     rc = lib.dtw_pairwise_ex(ctypes.byref(d), ctypes.byref(o))
     return rc, B.dtw_last_error()
 
@@ -77,10 +79,12 @@ def test_invalid_arguments_rejected_on_host():
     rc, msg = _call_ex(ok_len, ok_off, out=0)
     assert rc == B.DTW_ERR_INVALID_ARG and "out_condensed" in msg
     assert _call_ex(ok_len, ok_off, dtype=7)[0] == B.DTW_ERR_INVALID_ARG
-    assert _call_ex(ok_len, ok_off, accum=3)[0] == B.DTW_ERR_INVALID_ARG
+    assert _call_ex(ok_len, ok_off, accum=5)[0] == B.DTW_ERR_INVALID_ARG
+    assert _call_ex(ok_len, ok_off, accum=-1)[0] == B.DTW_ERR_INVALID_ARG
     assert _call_ex(ok_len, ok_off, kernel=9)[0] == B.DTW_ERR_INVALID_ARG
     assert _call_ex(ok_len, ok_off, flags=8)[0] == B.DTW_ERR_INVALID_ARG
-    assert _call_ex(ok_len, ok_off, kernel=3, accum=1)[0] == B.DTW_ERR_UNSUPPORTED  # cyclic needs PLAIN
+    for acc in (B.ACCUM["kahan"], B.ACCUM["fp64"]):  # the cyclic kernel has the plain FP32 cell only
+        assert _call_ex(ok_len, ok_off, kernel=3, accum=acc)[0] == B.DTW_ERR_UNSUPPORTED
     lib = B.load()
     assert lib.dtw_pairwise_ex(None, None) == B.DTW_ERR_INVALID_ARG
     assert lib.dtw_plan_destroy(None) == B.DTW_ERR_INVALID_ARG
@@ -160,13 +164,35 @@ def test_unsupported_requests_rejected_on_host():
     # forcing the lane-band kernel on unequal lengths
     rc, msg = _call_ex([4, 5, 4], [0, 4, 9], kernel=1)
     assert rc == B.DTW_ERR_UNSUPPORTED and "lane-band" in msg
-    # lane-band kernel with Kahan accumulation
-    assert _call_ex([4, 4], [0, 4], kernel=1, accum=1)[0] == B.DTW_ERR_UNSUPPORTED
+    # lane-band kernel with Kahan or FP64 accumulation
+    assert _call_ex([4, 4], [0, 4], kernel=1, accum=B.ACCUM["kahan"])[0] == B.DTW_ERR_UNSUPPORTED
+    assert _call_ex([4, 4], [0, 4], kernel=1, accum=B.ACCUM["fp64"])[0] == B.DTW_ERR_UNSUPPORTED
     # both series of a pair longer than the wavefront kernels cover
     rc, msg = _call_ex([40000, 40000], [0, 40000])
     assert rc == B.DTW_ERR_UNSUPPORTED and "32768" in msg
-    rc, msg = _call_ex([20000, 20000], [0, 20000], accum=1)
+    rc, msg = _call_ex([20000, 20000], [0, 20000], accum=B.ACCUM["kahan"])
     assert rc == B.DTW_ERR_UNSUPPORTED and "16384" in msg
+    rc, msg = _call_ex([40000, 40000], [0, 40000], accum=B.ACCUM["rebased"])
+    assert rc == B.DTW_ERR_UNSUPPORTED and "32768" in msg
+
+
+def test_accumulation_enum_matches_header():
+    text = open(HEADER).read()
+    for name, val in B.ACCUM.items():
+        assert re.search(r"DTW_ACC_%s\s*=\s*%d\b" % (name.upper(), val), text), name
+    # a zero-initialised dtw_options asks for AUTO accumulation
+    assert B.ACCUM["auto"] == 0
+
+
+def test_output_range_validated_on_host():
+    ok_len, ok_off = [4, 4, 4], [0, 4, 8]
+    rc, msg = _call_ex(ok_len, ok_off, k_range=(-1, 0))
+    assert rc == B.DTW_ERR_INVALID_ARG and "range" in msg
+    rc, msg = _call_ex(ok_len, ok_off, k_range=(2, 1))
+    assert rc == B.DTW_ERR_INVALID_ARG and "range" in msg
+    # the options struct carries the range after the stream pointer
+    assert B.dtw_options.k_begin.offset == 32 and B.dtw_options.k_end.offset == 40
+    assert ctypes.sizeof(B.dtw_options) == 48
 
 
 def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):

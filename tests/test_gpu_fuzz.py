@@ -5,10 +5,12 @@ Each case draws the series count, a length range (from one point up to past
 one wavefront's 64-row capacity), a window (none, zero, narrow, wide) and
 optionally equal lengths, so the planner's choices -- lane-band tiles, strip
 heights with and without window events, cyclic block heights -- and the
-ragged edges of each are exercised together.  The tolerance is the one of the
-parity tests: plain FP32 1e-5 up to 2048-cell paths and 1e-4 beyond, 16-bit
-inputs 1e-3, compensated sums 1e-5; FP64 mode bit-exact with the oracle
-rounded once; all families of one dataset agree bit for bit in plain FP32."""
+ragged edges of each are exercised together.  The tolerances are the ones of
+the parity tests: 1e-5 for FP32 inputs under the default accumulation (and
+under rebased or Kahan sums) at every path length, 1e-3 for 16-bit inputs;
+FP64 mode bit-exact with the oracle rounded once; explicitly plain FP32 sums
+1e-5 up to 2048-cell paths and 1e-4 beyond, and all families of one dataset
+agree bit for bit with them."""
 import numpy as np
 import pytest
 
@@ -43,10 +45,10 @@ def _case(seed):
 
 
 def _tol(ds, dtype, accum):
-    if accum != "plain":
-        return 1e-5
     if dtype != "f32":
         return 1e-3
+    if accum != "plain":
+        return 1e-5
     L = np.sort(np.asarray(ds.lengths, dtype=np.int64))
     return 1e-5 if int(L[-1] + L[-2] - 1) <= 2048 else 1e-4
 
@@ -72,7 +74,11 @@ def test_random_dataset_every_family(seed):
     narrow = ds.window >= 0 and 2 * ds.window + 1 <= 127
     plain = {}
     for kernel in ["auto", "wave", "cyclic"] + (["lane"] if equal and narrow else []):
-        got = B.pairwise(ds, kernel=kernel).cpu().numpy()
+        got = B.pairwise(ds, kernel=kernel).cpu().numpy()  # default accumulation
+        _check(got, ref, _tol(ds, dtype, "auto"), "seed %d %s default" % (seed, kernel))
+        got = B.pairwise(ds, kernel=kernel, accum="rebased").cpu().numpy()
+        _check(got, ref, _tol(ds, dtype, "rebased"), "seed %d %s rebased" % (seed, kernel))
+        got = B.pairwise(ds, kernel=kernel, accum="plain").cpu().numpy()
         _check(got, ref, _tol(ds, dtype, "plain"), "seed %d %s plain" % (seed, kernel))
         plain[kernel] = got
     first = plain["wave"]
