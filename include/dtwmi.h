@@ -175,6 +175,31 @@ int dtw_pairwise(const float *series, const int32_t *lengths, const int64_t *off
 int dtw_pairwise_ex(const dtw_dataset *ds, const dtw_options *opt);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * evaluation as dtw_pairwise_ex, with every device workspace -- the padded
+ * FP32 copy of the series, the series, dataset and work-item tables and the
+ * queue counters -- in a static device array of 32 MiB that the library holds
+ * on each device it runs on until the process ends.  It calls no allocating
+ * routine: the tables are built in a static host buffer and copied into that
+ * array with a synchronous copy on opt->stream (which waits for earlier work
+ * on that stream), then the kernels are enqueued and the call returns; the
+ * result is valid after the stream is synchronised.  The queue counters are
+ * cleared by a kernel on every call.  All calls on one device share the
+ * array: a call overwrites what the previous one left there, so calls whose
+ * work overlaps on one device (different streams, or threads without
+ * ordering) race and must not be made.
+ * Returns DTW_ERR_UNSUPPORTED when the dataset needs more than the array
+ * holds (the padded series take 4*(length + 256) bytes each, plus 24 bytes
+ * per work item: up to ~28 MB of series and items together), with
+ * DTW_FLAG_AUTOTUNE (it allocates) and with an output range other than 0, 0;
+ * otherwise it accepts and rejects what dtw_pairwise_ex does.  Kernel choice follows the cost
+ * model (no plan-wide grouping across calls); results equal those of
+ * dtw_pairwise_ex for the same options up to the rounding of rebased sums.
+ */
+int dtw_pairwise_noalloc(const dtw_dataset *ds, const dtw_options *opt);
+
+/*
  * Plans: validate, enumerate and tile all pairs of n_datasets datasets once,
  * allocate the device workspace and upload the tile lists.  The plan keeps
  * the dataset device pointers (series, out_condensed) and the caller keeps

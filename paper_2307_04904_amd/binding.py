@@ -22,7 +22,7 @@ DTW_FLAG_TIMING = 1
 DTW_FLAG_NO_QUEUE = 2
 DTW_FLAG_AUTOTUNE = 4
 
-EXPORTED = ["dtw_pairwise", "dtw_pairwise_ex", "dtw_plan_create", "dtw_plan_execute",
+EXPORTED = ["dtw_pairwise", "dtw_pairwise_ex", "dtw_pairwise_noalloc", "dtw_plan_create", "dtw_plan_execute",
             "dtw_plan_last_kernel_ms", "dtw_plan_info", "dtw_plan_describe", "dtw_plan_destroy", "dtw_band_cells",
             "dtw_plan_create_pairs", "dtw_pairs", "dtw_silhouette", "dtw_cluster_cost", "dtw_assign",
             "dtw_path", "dtw_last_error", "dtw_version"]
@@ -73,6 +73,7 @@ def load(path: str = LIB_PATH):
     i32p, i64p = P(ctypes.c_int32), P(ctypes.c_int64)
     lib.dtw_pairwise.argtypes = [ctypes.c_void_p, i32p, i64p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p]
     lib.dtw_pairwise_ex.argtypes = [P(dtw_dataset), P(dtw_options)]
+    lib.dtw_pairwise_noalloc.argtypes = [P(dtw_dataset), P(dtw_options)]
     lib.dtw_plan_create.argtypes = [P(ctypes.c_void_p), P(dtw_dataset), ctypes.c_int32, P(dtw_options)]
     lib.dtw_plan_execute.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
     lib.dtw_plan_last_kernel_ms.argtypes = [ctypes.c_void_p, P(ctypes.c_float)]
@@ -154,6 +155,15 @@ def dtw_pairwise(series, lengths, offsets, N, window, out_condensed):
     _check(load().dtw_pairwise(ctypes.c_void_p(series.data_ptr()), ln.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                                off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), int(N), int(window),
                                ctypes.c_void_p(out_condensed.data_ptr())))
+
+
+def dtw_pairwise_noalloc(series, lengths, offsets, window, out_condensed, dtype="f32", accum="auto", kernel="auto",
+                         stream=None):
+    """The allocation-free entry point (static device workspace), enqueued on `stream`."""
+    d, keep = _make_dataset(series, lengths, offsets, window, out_condensed)
+    o = _options(dtype, accum, kernel, 0, stream)
+    _check(load().dtw_pairwise_noalloc(ctypes.byref(d), ctypes.byref(o)))
+    del keep
 
 
 def dtw_pairwise_ex(series, lengths, offsets, window, out_condensed, dtype="f32", accum="auto", kernel="auto",

@@ -1044,6 +1044,192 @@ int cached_run(const dtw_dataset &d, const dtw_options *opt, const PairRequest *
     return DTW_OK;
 }
 
+// ---- allocation-free evaluation (dtw_pairwise_noalloc) ----
+// The whole device workspace of one call -- padded FP32 copy of the series,
+// series and dataset tables, work items, queue counters -- lives in this
+// file-scope array, one copy per device the library runs on, held until the
+// process ends.  Its address on the current device comes from
+// hipGetSymbolAddress (the array's name is only a host-side stand-in); the
+// tables are built in a static host buffer of the same role and copied in.
+// Calls share the array and the host buffer: a lock serialises the host part,
+// and calls on different streams of one device race on the device part.
+constexpr size_t kScratchBytes = size_t(32) << 20;   // device workspace of one call
+constexpr size_t kHostStageBytes = size_t(64) << 20; // tables plus the planner's sort records
+constexpr int kMaxScratchDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+alignas(256) unsigned char g_host_stage[kHostStageBytes];
+std::mutex g_noalloc_mu;
+void *g_scratch_ptr[kMaxScratchDevices];  // device address of `scratch` per device, set once
+
+// Sort record of a wavefront pair: its kernel instance and cost.
+struct NoAllocRec {
+    uint32_t kind;  // (((H * 32 + G) * 2 + banded) * 4 + acc)
+    int64_t cost;
+    WaveItem item;
+};
+
+int noalloc_run(const dtw_dataset &d, const dtw_options &o) {
+    if (o.flags & DTW_FLAG_AUTOTUNE)
+        return fail(DTW_ERR_UNSUPPORTED, "DTW_FLAG_AUTOTUNE allocates; the allocation-free entry point refuses it");
+    if (o.k_begin != 0 || o.k_end != 0)
+        return fail(DTW_ERR_UNSUPPORTED, "the allocation-free entry point evaluates every pair (k_begin = k_end = 0)");
+    const int32_t N = d.N;
+    const bool use_queue = !(o.flags & DTW_FLAG_NO_QUEUE);
+
+    // ---- sizes (no HIP calls yet) ----
+    size_t ws_floats = 0;
+    bool uniform = true;
+    for (int32_t s = 0; s < N; ++s) {
+        ws_floats += align_up(static_cast<size_t>(d.lengths[s]) + 2 * kPad, 4);
+        uniform = uniform && d.lengths[s] == d.lengths[0];
+    }
+    ws_floats += 256;
+    int lane_w = 0;
+    const int lane_acc = uniform ? pair_acc(o.accum, d.lengths[0], d.lengths[0]) : kAccPlain;
+    if (uniform && plain_cell(lane_acc) && o.kernel != DTW_KERNEL_WAVE && o.kernel != DTW_KERNEL_CYCLIC) {
+        const int32_t L = d.lengths[0];
+        const int32_t b = (d.window < 0 || d.window >= L - 1) ? L - 1 : d.window;
+        if (lane_width_supported(2 * b + 1)) lane_w = 2 * b + 1;
+    }
+    if (o.kernel == DTW_KERNEL_LANE && !lane_w)
+        return fail(DTW_ERR_UNSUPPORTED,
+                    "the lane-band kernel needs equal lengths, PLAIN or REBASED accumulation and 2*w+1 <= %d",
+                    kLaneMaxW);
+    int64_t n_lane = 0;
+    const int64_t n_pairs = (int64_t)N * (N - 1) / 2;
+    if (lane_w)
+        for (int32_t a = 0; a < N; ++a) {
+            const int32_t h = (N % 2 == 0 && a < N / 2) ? N / 2 : (N - 1) / 2;
+            n_lane += (h + 63) / 64;
+        }
+    const size_t o_ws = 0;
+    size_t off = align_up(ws_floats * sizeof(float), 256);
+    const size_t o_src = off;
+    off = align_up(off + N * sizeof(SeriesSrc), 256);
+    const size_t o_ser = off;
+    off = align_up(off + N * sizeof(SeriesInfo), 256);
+    const size_t o_ds = off;
+    off = align_up(off + sizeof(DatasetInfo), 256);
+    const size_t o_items = off;
+    off = align_up(off + (lane_w ? n_lane * sizeof(LaneItem) : n_pairs * sizeof(WaveItem)), 256);
+    const size_t o_queue = off;
+    off = align_up(off + kMaxQueues * sizeof(unsigned), 256);
+    const size_t need = off;
+    const size_t o_sort = align_up(o_queue - o_src, 256);  // host staging: tables, then sort records
+    const size_t host_need = o_sort + (lane_w ? 0 : n_pairs * sizeof(NoAllocRec));
+    if (need > kScratchBytes || host_need > kHostStageBytes)
+        return fail(DTW_ERR_UNSUPPORTED,
+                    "the allocation-free entry point holds %zu bytes of device workspace (and %zu of host tables); "
+                    "this dataset needs %zu (%zu)",
+                    kScratchBytes, kHostStageBytes, need, host_need);
+
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    // ---- tables, built in the host staging buffer at their device offsets minus o_src ----
+    unsigned char *h = g_host_stage;
+    SeriesSrc *hsrc = reinterpret_cast<SeriesSrc *>(h + (o_src - o_src));
+    SeriesInfo *hser = reinterpret_cast<SeriesInfo *>(h + (o_ser - o_src));
+    DatasetInfo *hds = reinterpret_cast<DatasetInfo *>(h + (o_ds - o_src));
+    size_t wsf = 0;
+    for (int32_t s = 0; s < N; ++s) {
+        hsrc[s] = SeriesSrc{d.series, d.offsets[s], d.lengths[s], o.dtype};
+        hser[s] = SeriesInfo{static_cast<int64_t>(wsf) + kPad, d.lengths[s], 0};
+        wsf += align_up(static_cast<size_t>(d.lengths[s]) + 2 * kPad, 4);
+    }
+    *hds = DatasetInfo{d.out_condensed, N, d.window, uniform ? d.lengths[0] : -1, 0};
+    struct Group {
+        uint32_t kind;
+        int64_t begin, count;
+    } groups[kMaxQueues];
+    int n_groups = 0;
+    if (lane_w) {
+        LaneItem *it = reinterpret_cast<LaneItem *>(h + (o_items - o_src));
+        int64_t k = 0;
+        for (int32_t a = 0; a < N; ++a) {
+            const int32_t hh = (N % 2 == 0 && a < N / 2) ? N / 2 : (N - 1) / 2;
+            for (int32_t d0 = 1; d0 <= hh; d0 += 64) it[k++] = LaneItem{0, a, d0, std::min(64, hh - d0 + 1), -1};
+        }
+    } else {
+        NoAllocRec *rec = reinterpret_cast<NoAllocRec *>(h + o_sort);
+        int64_t k = 0;
+        for (int32_t i = 0; i < N - 1; ++i)
+            for (int32_t j = i + 1; j < N; ++j, ++k) {
+                const int32_t ni = d.lengths[i], nj = d.lengths[j];
+                const bool swap = nj < ni;
+                WavePair w{0, swap ? j : i, swap ? i : j, std::min(ni, nj), std::max(ni, nj), 0, k, 0};
+                w.b = static_cast<int32_t>(effective_band(d.window, w.n, w.m));
+                w.acc = pair_acc(o.accum, w.n, w.m);
+                const Choice c = model_choice(o.kernel, o.rows_per_lane, w);
+                if (!c.H)
+                    return fail(DTW_ERR_UNSUPPORTED, "pair (%d,%d) (%d x %d points, band %d): no kernel fits it", i,
+                                j, w.n, w.m, w.b);
+                const uint32_t banded = (c.cyclic() || w.b >= 0) ? 1u : 0u;
+                rec[k] = NoAllocRec{(((uint32_t)c.H * 32u + (uint32_t)c.G) * 2u + banded) * 4u + (uint32_t)w.acc,
+                                    choice_cost(c, w), make_item(c, w)};
+            }
+        // group by instance, costliest pairs first (in place: no allocation)
+        std::sort(rec, rec + n_pairs, [](const NoAllocRec &a, const NoAllocRec &b) {
+            return a.kind != b.kind ? a.kind < b.kind : a.cost > b.cost;
+        });
+        WaveItem *it = reinterpret_cast<WaveItem *>(h + (o_items - o_src));
+        for (int64_t q = 0; q < n_pairs; ++q) {
+            if (q == 0 || rec[q].kind != rec[q - 1].kind) {
+                if (n_groups == kMaxQueues) return fail(DTW_ERR_UNSUPPORTED, "more than %d kernel groups", kMaxQueues);
+                groups[n_groups++] = Group{rec[q].kind, q, 0};
+            }
+            ++groups[n_groups - 1].count;
+            it[q] = rec[q].item;
+        }
+    }
+
+    // ---- device part: scratch address, one table copy, launches ----
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxScratchDevices) return fail(DTW_ERR_UNSUPPORTED, "device %d out of range", dev);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        if ((e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch))) != hipSuccess)
+            return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        g_scratch_ptr[dev] = ptr;
+    }
+    unsigned char *base = static_cast<unsigned char *>(g_scratch_ptr[dev]);
+    hipStream_t st = static_cast<hipStream_t>(o.stream);
+    // synchronous copy: the host buffer is free again when it returns
+    if ((e = hipMemcpyWithStream(base + o_src, h, o_queue - o_src, hipMemcpyHostToDevice, st)) != hipSuccess)
+        return hip_fail(e, "table copy into the scratch array");
+    float *ws = reinterpret_cast<float *>(base + o_ws);
+    SeriesSrc *dsrc = reinterpret_cast<SeriesSrc *>(base + o_src);
+    SeriesInfo *dser = reinterpret_cast<SeriesInfo *>(base + o_ser);
+    DatasetInfo *dds = reinterpret_cast<DatasetInfo *>(base + o_ds);
+    unsigned *dq = reinterpret_cast<unsigned *>(base + o_queue);
+    if ((e = launch_stage(dsrc, dser, ws, N, st)) != hipSuccess) return hip_fail(e, "staging kernel launch");
+    if (lane_w) {
+        if ((e = launch_lane(lane_w, lane_acc == kAccRebased, ws, dser, dds,
+                             reinterpret_cast<LaneItem *>(base + o_items), nullptr, (unsigned)n_lane, st)) != hipSuccess)
+            return hip_fail(e, "lane-band kernel launch");
+        return DTW_OK;
+    }
+    if (use_queue && (e = launch_zero(dq, n_groups, st)) != hipSuccess)  // counters start at zero every call
+        return hip_fail(e, "queue reset kernel launch");
+    const WaveItem *ditems = reinterpret_cast<const WaveItem *>(base + o_items);
+    for (int g = 0; g < n_groups; ++g) {
+        const uint32_t kind = groups[g].kind;
+        const int acc = (int)(kind % 4u), banded = (int)((kind / 4u) % 2u);
+        const int G = (int)((kind / 8u) % 32u), H = (int)(kind / 256u);
+        unsigned *queue = use_queue ? dq + g : nullptr;
+        if (G == 0)
+            e = launch_cyclic(H, acc == kAccRebased, ws, dser, dds, ditems + groups[g].begin,
+                              (unsigned)groups[g].count, queue, use_queue ? cyclic_resident(H, acc == kAccRebased) : 0,
+                              st);
+        else
+            e = launch_strip(acc, StripShape{H, G}, banded != 0, ws, dser, dds, ditems + groups[g].begin,
+                             (unsigned)groups[g].count, queue,
+                             use_queue ? strip_resident(acc, StripShape{H, G}, banded != 0) : 0, st);
+        if (e != hipSuccess) return hip_fail(e, "wavefront kernel launch");
+    }
+    return DTW_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1223,6 +1409,18 @@ int dtw_pairs(const dtw_dataset *ds, const dtw_pair *pairs, int64_t n_pairs, flo
     if (n_pairs == 0) return DTW_OK;  // nothing to write, no HIP call
     const PairRequest req{pairs, n_pairs, out};
     return cached_run(*ds, opt, &req);
+}
+
+int dtw_pairwise_noalloc(const dtw_dataset *ds, const dtw_options *opt) {
+    g_err.clear();
+    if (!ds) return fail(DTW_ERR_INVALID_ARG, "dataset is NULL");
+    int rc = validate_options(opt);
+    if (rc) return rc;
+    if ((rc = validate_dataset(*ds, 0))) return rc;
+    if (ds->N < 2) return DTW_OK;  // nothing to write, no HIP call
+    dtw_options o{};
+    if (opt) o = *opt;
+    return noalloc_run(*ds, o);
 }
 
 int dtw_pairwise(const float *series, const int32_t *lengths, const int64_t *offsets, int32_t N, int32_t window,
