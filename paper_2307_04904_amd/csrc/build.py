@@ -13,7 +13,7 @@ PKG = os.path.dirname(HERE)
 ROOT = os.path.dirname(PKG)
 OUT_DIR = os.path.join(PKG, "_build")
 LIB = os.path.join(OUT_DIR, "libdtwmi.so")
-SOURCES = ["dtw_stage.hip", "dtw_lane.hip", "dtw_lane_rb.hip", "dtw_strip.hip", "dtw_cyclic.hip", "dtw_cluster.hip", "dtw_path.hip", "dtw_api.hip"]
+SOURCES = ["dtw_stage.hip", "dtw_lane.hip", "dtw_lane_rb.hip", "dtw_strip.hip", "dtw_strip_f64.hip", "dtw_cyclic.hip", "dtw_cluster.hip", "dtw_path.hip", "dtw_api.hip"]
 ARCH = os.environ.get("DTWMI_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [
@@ -42,6 +42,10 @@ def _run(cmd, verbose):
         print("\n".join(msgs))
 
 
+# per-source flags: the FP64 strips produce no NaN, so they drop signalling-NaN handling
+EXTRA = {"dtw_strip_f64.hip": ["-fno-honor-nans", "-mno-amdgpu-ieee"]}
+
+
 def build(verbose: bool = False, jobs: int = 0) -> str:
     """Compile every source to an object (in parallel), then link the shared library."""
     from concurrent.futures import ThreadPoolExecutor
@@ -49,7 +53,8 @@ def build(verbose: bool = False, jobs: int = 0) -> str:
     inc = ["-I", os.path.join(ROOT, "include"), "-I", HERE]
     tag = "%d" % os.getpid()
     objs = [os.path.join(OUT_DIR, os.path.splitext(s)[0] + ".o." + tag) for s in SOURCES]
-    cmds = [["hipcc"] + FLAGS + inc + ["-c", os.path.join(HERE, s), "-o", o] for s, o in zip(SOURCES, objs)]
+    cmds = [["hipcc"] + FLAGS + EXTRA.get(s, []) + inc + ["-c", os.path.join(HERE, s), "-o", o]
+            for s, o in zip(SOURCES, objs)]
     jobs = jobs or min(len(cmds), os.cpu_count() or 1, 8)
     try:
         with ThreadPoolExecutor(max_workers=jobs) as pool:

@@ -97,15 +97,29 @@ int64_t condensed_host(int32_t i, int32_t j, int32_t N) {
     return a * N - a * (a + 1) / 2 + (b - a - 1);
 }
 
-// Accumulation of one pair (AccMode) under the public mode.
-constexpr int64_t kAutoPlainMaxPath = 2048;  // longest path summed plainly under AUTO
-int pair_acc(int accum, int64_t n, int64_t m) {
+// Accumulation of one pair (AccMode) under the public mode; b is the pair's
+// effective band (-1: none).  AUTO: plain sums up to 2048-cell warping paths;
+// beyond, rebased sums for pairs with a window (the frontier stays near the
+// path: measured ~10x below plain sums at 8,191-cell paths) and for
+// unwindowed paths up to 4096 cells; unwindowed longer paths, where the
+// cheapest frontier cell can lie far below the path and rebased sums gain
+// less, run in FP64 (the oracle's operations, rounded once) while the shorter
+// series fits an FP64 strip shape.
+constexpr int64_t kAutoPlainMaxPath = 2048;
+constexpr int64_t kAutoRebasedMaxPathNoWindow = 4096;
+int max_strip_rows(int accum);
+int pair_acc(int accum, int64_t n, int64_t m, int64_t b) {
     switch (accum) {
         case DTW_ACC_PLAIN: return kAccPlain;
         case DTW_ACC_KAHAN: return kAccKahan;
         case DTW_ACC_FP64: return kAccF64;
         case DTW_ACC_REBASED: return kAccRebased;
-        default: return n + m - 1 <= kAutoPlainMaxPath ? kAccPlain : kAccRebased;
+        default: {
+            const int64_t path = n + m - 1;
+            if (path <= kAutoPlainMaxPath) return kAccPlain;
+            if (b >= 0 || path <= kAutoRebasedMaxPathNoWindow) return kAccRebased;
+            return std::min(n, m) <= max_strip_rows(kAccF64) ? kAccF64 : kAccRebased;
+        }
     }
 }
 // Modes with the plain FP32 cell, which the lane-band and cyclic kernels run.
@@ -635,7 +649,9 @@ int plan_build(dtw_plan *plan_out, const dtw_dataset *ds, int32_t n_datasets, co
 
         // Kernel family for this dataset.
         int lane_w = 0;
-        const int lane_acc = uniform ? pair_acc(accum, D.lengths[0], D.lengths[0]) : kAccPlain;
+        const int lane_acc =
+            uniform ? pair_acc(accum, D.lengths[0], D.lengths[0], effective_band(D.window, D.lengths[0], D.lengths[0]))
+                    : kAccPlain;
         if (uniform && plain_cell(lane_acc)) {
             const int32_t L = D.lengths[0];
             const int32_t b = (D.window < 0 || D.window >= L - 1) ? L - 1 : D.window;
@@ -722,7 +738,7 @@ int plan_build(dtw_plan *plan_out, const dtw_dataset *ds, int32_t n_datasets, co
                                std::max(ni, nj), 0, 0, 0};
                     w.slot = k;
                     w.b = static_cast<int32_t>(effective_band(D.window, w.n, w.m));
-                    w.acc = pair_acc(accum, w.n, w.m);
+                    w.acc = pair_acc(accum, w.n, w.m, w.b);
                     st.band_cells += band_cells(w.n, w.m, w.b);
                     if (!model_choice(kernel, force_h, w).H) {
                         if (force_h > 0)
@@ -1085,7 +1101,9 @@ int noalloc_run(const dtw_dataset &d, const dtw_options &o) {
     }
     ws_floats += 256;
     int lane_w = 0;
-    const int lane_acc = uniform ? pair_acc(o.accum, d.lengths[0], d.lengths[0]) : kAccPlain;
+    const int lane_acc =
+        uniform ? pair_acc(o.accum, d.lengths[0], d.lengths[0], effective_band(d.window, d.lengths[0], d.lengths[0]))
+                : kAccPlain;
     if (uniform && plain_cell(lane_acc) && o.kernel != DTW_KERNEL_WAVE && o.kernel != DTW_KERNEL_CYCLIC) {
         const int32_t L = d.lengths[0];
         const int32_t b = (d.window < 0 || d.window >= L - 1) ? L - 1 : d.window;
@@ -1157,7 +1175,7 @@ int noalloc_run(const dtw_dataset &d, const dtw_options &o) {
                 const bool swap = nj < ni;
                 WavePair w{0, swap ? j : i, swap ? i : j, std::min(ni, nj), std::max(ni, nj), 0, k, 0};
                 w.b = static_cast<int32_t>(effective_band(d.window, w.n, w.m));
-                w.acc = pair_acc(o.accum, w.n, w.m);
+                w.acc = pair_acc(o.accum, w.n, w.m, w.b);
                 const Choice c = model_choice(o.kernel, o.rows_per_lane, w);
                 if (!c.H)
                     return fail(DTW_ERR_UNSUPPORTED, "pair (%d,%d) (%d x %d points, band %d): no kernel fits it", i,

@@ -266,8 +266,9 @@ def test_long_series_precision_modes(dtype, accum):
     got = run(ds, accum=accum)
     g = got[condensed(pi, pj, ds.N)]
     print("500x4096 %s %s: %d pairs" % (dtype, accum, len(pi)), flush=True)
-    if accum == "fp64":
-        assert np.array_equal(g, ref.astype(np.float32)), "FP64 mode must equal the oracle rounded to FP32"
+    if accum == "fp64" or accum == "auto":
+        # the default runs these unwindowed 8,191-cell paths in FP64
+        assert np.array_equal(g, ref.astype(np.float32)), "FP64 sums must equal the oracle rounded to FP32"
     elif dtype != "f32":
         assert_close(g, ref, tol=REL_TOL_16BIT, what="500x4096 %s %s" % (dtype, accum))
     elif accum == "plain":
@@ -661,20 +662,33 @@ def test_lane_kernel_rebased_long_series(window):
 
 
 def test_auto_splits_accumulation_by_path_length():
-    # pairs whose longest path has at most 2048 cells keep plain sums (bit-equal to an
-    # explicit plain plan), longer ones get rebased sums; both within 1e-5
+    # without a window: pairs whose longest path has at most 2048 cells keep plain sums
+    # (bit-equal to an explicit plain plan), paths up to 4096 cells get rebased sums and
+    # longer ones FP64 (the oracle rounded once, bit for bit); all within 1e-5
     _gpu()
     rng = np.random.default_rng(1300)
-    lens = [600, 1000, 1049, 1100, 2000, 300]
+    lens = [600, 1000, 1049, 1100, 2000, 300, 2500]
     ds = synth.pack([synth.random_walk(rng, L) for L in lens], "split", -1)
     auto, _ = _run_plan(ds)
     plain, _ = _run_plan(ds, accum="plain")
+    plan, _, _ = _plan_for([ds])
+    accs = {g["accum"] for g in plan.describe()["wave_groups"]}
+    plan.destroy()
+    assert accs == {"plain", "rebased", "fp64"}, accs
     pi, pj = oracle.all_pairs_list(ds.N)
     ref = oracle_pairs(ds, pi, pj)
     assert_close(auto, ref, what="auto split")
-    short = np.array([lens[a] + lens[b] - 1 <= 2048 for a, b in zip(pi, pj)])
-    assert 0 < short.sum() < len(short)
-    assert np.array_equal(auto[short], plain[short])
+    path = np.array([lens[a] + lens[b] - 1 for a, b in zip(pi, pj)])
+    assert np.array_equal(auto[path <= 2048], plain[path <= 2048])
+    assert np.array_equal(auto[path > 4096], ref[path > 4096].astype(np.float32))
+    # with a window, long paths keep rebased sums (no FP64 groups)
+    dsw = synth.pack([synth.random_walk(rng, L) for L in lens], "splitw", 200)
+    plan, _, _ = _plan_for([dsw])
+    accs = {g["accum"] for g in plan.describe()["wave_groups"]}
+    plan.destroy()
+    assert "fp64" not in accs and "rebased" in accs, accs
+    got, _ = _run_plan(dsw)
+    assert_close(got, oracle_pairs(dsw, pi, pj), what="auto split, window 200")
 
 
 def _range_out(ds, k_range, **kw):
