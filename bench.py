@@ -38,8 +38,9 @@ OPS_PER_CELL = 3
 # Per accumulation mode: VALU lane-operations of the recurrence per admissible
 # cell and the peak they run against.
 #   plain: v_sub, v_min3, v_fma (the square fused into the add)
-#   kahan: sub, mul, min3, two compares and two selects picking the carried
-#          compensation, then Kahan's add: sub, add, sub, sub  (11)
+#   kahan: sub, min3, three compares, three selects and a max3 picking the
+#          carried compensation (the largest among tied sums), then Kahan's
+#          add: fma (square minus compensation), add, sub, sub  (13)
 #   fp64:  sub, mul, min, min, add in FP64 (5), against the FP64 vector peak
 #          78.6 TFLOP/s = 39.32 T lane-ops/s (an FMA counted as one op)
 PEAK_FP64_LANE_OPS_T = 78.6 / 2
@@ -49,12 +50,12 @@ PEAK_FP64_LANE_OPS_T = 78.6 / 2
 MODE_OPS = {"plain": (3, PEAK_LANE_OPS_T, "TOP/s (FP32 VALU lane-ops)"),
             "auto": (3, PEAK_LANE_OPS_T, "TOP/s (FP32 VALU lane-ops)"),
             "rebased": (3, PEAK_LANE_OPS_T, "TOP/s (FP32 VALU lane-ops)"),
-            "kahan": (11, PEAK_LANE_OPS_T, "TOP/s (FP32 VALU lane-ops)"),
+            "kahan": (13, PEAK_LANE_OPS_T, "TOP/s (FP32 VALU lane-ops)"),
             "fp64": (5, PEAK_FP64_LANE_OPS_T, "TOP/s (FP64 VALU lane-ops)")}
 # profile summary (profiles/<label>*.md) holding the counter-based HBM traffic of a workload's DP kernel
 PROFILE_LABELS = {("c2", "auto", "auto", "f32"): "lane_band_W103_c2",
                   ("c5", "auto", "auto", "f32"): "lane_band_W51_c5",
-                  ("c3", "auto", "auto", "f32"): "strip_rebased_H64_c3",
+                  ("c3", "auto", "auto", "f32"): "strip_f64_H16x4_c3",
                   ("c4", "auto", "auto", "f32"): "batched_c4"}
 
 WORKLOADS = {
@@ -391,7 +392,13 @@ def main(argv=None):
 
     cells = info["band_cells"]
     value = cells / (ms_per_step * 1e-3) / 1e9
-    ops_cell, peak, peak_unit = MODE_OPS[args.accum]
+    # the roofline of the accumulation the plan actually runs (AUTO resolves per pair:
+    # all-FP64 plans against the FP64 peak, otherwise the FP32 cell)
+    accs = {g["accum"] for g in plan_desc["wave_groups"]} | {g["accum"] for g in plan_desc["lane_groups"]}
+    mode = args.accum
+    if mode == "auto":
+        mode = "fp64" if accs == {"fp64"} else ("kahan" if accs == {"kahan"} else "auto")
+    ops_cell, peak, peak_unit = MODE_OPS[mode]
     achieved = ops_cell * cells / (k_avg * 1e-3) / 1e12
     line = {
         "metric": "DTW cell updates/s (GCUPS) for all-pairs matrix; % of FP32 VALU peak",
@@ -404,7 +411,7 @@ def main(argv=None):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.accum == "fp64" else "f32",
+        "dtype": "f64" if mode == "fp64" else "f32",
         "data": "synthetic",
         "timing": "hip graph replays" if args.graph else "eager executes",
         "config": {"workload": (dsets[0].name + ("_medoids%d" % MEDOIDS if pair_list is not None else "")
@@ -414,7 +421,8 @@ def main(argv=None):
                    "length": int(max(ds.lengths.max() for ds in dsets)),
                    "window": [ds.window for ds in dsets] if len(dsets) > 1 else dsets[0].window,
                    "pairs": info["pairs"], "band_cells": cells, "swept_cells": info["computed_cells"],
-                   "kernel": args.kernel, "accum": args.accum, "storage": dsets[0].dtype,
+                   "kernel": args.kernel, "accum": args.accum, "accum_groups": sorted(accs),
+                   "storage": dsets[0].dtype,
                    "dispatch": args.dispatch, "autotune": args.autotune, "rows_per_lane": args.rows_per_lane,
                    "kernels": ["%s/%s" % (g["kernel"], g["accum"]) for g in plan_desc["wave_groups"]] +
                               ["lane:%d/%s" % (g["W"], g["accum"]) for g in plan_desc["lane_groups"]],

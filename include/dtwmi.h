@@ -25,9 +25,12 @@
  *   - All arguments are validated on the host before any HIP call.
  *   - Series values must be finite; results for NaN or inf inputs are
  *     unspecified.  The output is always FP32.
- *   - Series may have any length >= 1.  The shorter series of a pair may have
- *     up to 32768 points with AUTO, PLAIN or REBASED accumulation and up to
- *     16384 with KAHAN or FP64; longer returns DTW_ERR_UNSUPPORTED.
+ *   - Series may have any length from 1 to 2^28 points (longer returns
+ *     DTW_ERR_UNSUPPORTED).  A pair whose shorter series has more rows than one
+ *     workgroup holds (32768 points with PLAIN or REBASED sums, 16384 with
+ *     KAHAN or FP64) is swept in row passes through a device buffer the plan
+ *     allocates (one row of the longer series per resident workgroup);
+ *     dtw_pairwise_noalloc rejects such pairs.  dtw_path has its own limit.
  */
 #ifndef DTWMI_H
 #define DTWMI_H
@@ -55,14 +58,14 @@ typedef enum { DTW_F32 = 0, DTW_BF16 = 1, DTW_F16 = 2 } dtw_dtype;
  *   AUTO:    (the default, 0) per pair: PLAIN when the longest warping path,
  *            n+m-1 cells, has at most 2048 cells; beyond, REBASED when the
  *            pair has a window (max(w, |n-m|) < max(n,m)-1) or the path has
- *            at most 4096 cells; longer unwindowed paths FP64 (REBASED when
- *            the shorter series exceeds 16384 points).
+ *            at most 4096 cells; longer unwindowed paths FP64.
  *   PLAIN:   FP32 sub, min, fused multiply-add per cell.  Each add rounds
  *            relative to the whole cumulative cost, so the error grows with
  *            the path length: within 1e-5 up to paths of 2048 cells, about
  *            1e-5 at 8191 (4096-point series), within 1e-4 beyond.
  *   KAHAN:   FP32 with a compensation term carried per cell and a compensated
- *            add of every local cost (the min compares the running sums).
+ *            add of every local cost (the min takes the smallest running sum
+ *            and, among equal sums, the largest compensation).
  *   FP64:    the whole recurrence in FP64, the final cost rounded once to FP32.
  *   REBASED: the PLAIN cell on values stored relative to a base that each
  *            wavefront (each lane, in the lane-band kernel) moves up every few
@@ -196,8 +199,9 @@ int dtw_pairwise_ex(const dtw_dataset *ds, const dtw_options *opt);
  * Returns DTW_ERR_UNSUPPORTED when the dataset needs more than the array
  * holds (the padded series take 4*(length + 256) bytes each, plus 24 bytes
  * per work item: up to ~28 MB of series and items together), with
- * DTW_FLAG_AUTOTUNE (it allocates) and with an output range other than 0, 0;
- * otherwise it accepts and rejects what dtw_pairwise_ex does.  Kernel choice follows the cost
+ * DTW_FLAG_AUTOTUNE (it allocates), with an output range other than 0, 0 and
+ * for a pair swept in row passes (see the length rule above: the pass buffer
+ * would not fit the array); otherwise it accepts and rejects what dtw_pairwise_ex does.  Kernel choice follows the cost
  * model (no plan-wide grouping across calls); results equal those of
  * dtw_pairwise_ex for the same options up to the rounding of rebased sums.
  */

@@ -4,12 +4,9 @@
 // Pair enumeration.  The paper computes all p(p-1)/2 pairwise distances
 // ("Mathematical background") and fills the symmetric matrix D.  This library
 // writes each unordered pair once into the condensed upper triangle.
-//  * lane-band datasets (all series of equal length, narrow band, PLAIN):
-//    series a is paired with the series at cyclic distances 1..h_a
-//    ((a+d) mod N), h_a = floor((N-1)/2), plus the pair at distance N/2 for
-//    a < N/2 when N is even.  Every unordered pair appears exactly once and
-//    every series gets the same number of partners, so the 64-pair work items
-//    are almost all full.
+//  * lane-band datasets (all series of equal length, narrow band, plain or
+//    rebased sums): tiles of up to 64 pairs at consecutive cyclic distances
+//    from one series (lane_cyclic_tiles).
 //  * wavefront datasets: one item per pair (i<j).  Each pair goes either to a
 //    strip kernel (the shorter series spread over the lanes, every column
 //    swept) or, with PLAIN accumulation and a window, to the cyclic kernel
@@ -18,8 +15,12 @@
 //    Items are grouped by kernel instance and each group is sorted by
 //    decreasing cost, so the longest pairs start first.
 //  * accumulation: AUTO gives each pair plain FP32 sums when its longest
-//    warping path (n+m-1 cells) has at most 2048 cells and rebased FP32 sums
-//    beyond, where plain sums approach the 1e-5 accuracy target.
+//    warping path (n+m-1 cells) has at most 2048 cells, beyond that rebased
+//    FP32 sums when the pair has a window or the path has at most 4096
+//    cells, and FP64 sums otherwise (pair_acc).
+//  * strip pairs whose shorter series exceeds the rows of the largest
+//    workgroup shape are swept in row passes through a per-workgroup buffer
+//    that the plan allocates.
 //  * a condensed sub-range [k_begin, k_end) restricts a plan to those output
 //    entries: lane-band datasets are then tiled by rows of the condensed
 //    matrix (runs of up to 64 consecutive partners j of one series i), the
@@ -103,11 +104,9 @@ int64_t condensed_host(int32_t i, int32_t j, int32_t N) {
 // path: measured ~10x below plain sums at 8,191-cell paths) and for
 // unwindowed paths up to 4096 cells; unwindowed longer paths, where the
 // cheapest frontier cell can lie far below the path and rebased sums gain
-// less, run in FP64 (the oracle's operations, rounded once) while the shorter
-// series fits an FP64 strip shape.
+// less, run in FP64 (the oracle's operations, rounded once).
 constexpr int64_t kAutoPlainMaxPath = 2048;
 constexpr int64_t kAutoRebasedMaxPathNoWindow = 4096;
-int max_strip_rows(int accum);
 int pair_acc(int accum, int64_t n, int64_t m, int64_t b) {
     switch (accum) {
         case DTW_ACC_PLAIN: return kAccPlain;
@@ -118,7 +117,7 @@ int pair_acc(int accum, int64_t n, int64_t m, int64_t b) {
             const int64_t path = n + m - 1;
             if (path <= kAutoPlainMaxPath) return kAccPlain;
             if (b >= 0 || path <= kAutoRebasedMaxPathNoWindow) return kAccRebased;
-            return std::min(n, m) <= max_strip_rows(kAccF64) ? kAccF64 : kAccRebased;
+            return kAccF64;
         }
     }
 }
@@ -140,6 +139,27 @@ int64_t effective_band(int32_t w, int32_t n, int32_t m) {
     return b >= std::max(n, m) - 1 ? -1 : b;
 }
 
+// Lane-band tiles of all pairs of an N-series dataset: series a is paired
+// with the series at cyclic distances 1..h_a, (a + d) mod N, h_a =
+// floor((N-1)/2), plus the pair at distance N/2 for a < N/2 when N is even,
+// so that every unordered pair appears once and every series has the same
+// number of partners (tiles of 64 partners, almost all full).  The tiles are
+// emitted distance-run by distance-run (first partner distance d0 = 1, 65,
+// 129, ...), every series within a run: consecutive tiles (a, d0) and
+// (a+1, d0) share 63 of their 64 row series, which keeps a wavefront's reads
+// in the L2 of its XCD (the kernel hands each XCD a contiguous range of
+// tiles).  Calls emit(a, d0, cnt) for the partners (a + d0 + lane) mod N,
+// lane < cnt.
+template <class F>
+void lane_cyclic_tiles(int32_t N, F emit) {
+    const int32_t hmax = N / 2;  // the most partners of one series
+    for (int32_t d0 = 1; d0 <= hmax; d0 += 64)
+        for (int32_t a = 0; a < N; ++a) {
+            const int32_t h = (N % 2 == 0 && a < N / 2) ? N / 2 : (N - 1) / 2;
+            if (d0 <= h) emit(a, d0, std::min(64, h - d0 + 1));
+        }
+}
+
 struct LaneGroup {
     int W;
     bool rebased;
@@ -154,6 +174,9 @@ struct WaveGroup {
     int slots = 0;           // resident workgroups of the kernel (queue mode)
     int64_t band_cells = 0;  // admissible cells of the group's pairs
     int64_t swept_cells = 0; // cells its kernel sweeps, padding included
+    int64_t max_rows = 0, max_cols = 0;  // longest series spread over the lanes / swept
+    void *pass_buf = nullptr;            // row-pass buffer of a strip group with pairs over 64*H*G rows
+    int64_t pass_stride = 0;             // its values per workgroup
 };
 
 
@@ -191,10 +214,16 @@ int64_t cal_factor(int H, bool banded) {
     return banded ? 190 : 130;
 }
 
-// Steps a strip workgroup takes on an n x m pair (n = rows spread over lanes).
+// Steps a strip workgroup takes on an n x m pair (n = rows spread over lanes),
+// over all its row passes of 64*H*G rows.
 int64_t strip_steps(StripShape sh, int64_t n, int64_t m) {
-    const int64_t lanes = (n - 1) / sh.H;  // last lane holding a row
-    return m + lanes % 64 + (lanes / 64) * (64 + (sh.G > 1 ? 16 : 0));
+    const int64_t cap = (int64_t)64 * sh.H * sh.G;
+    int64_t steps = 0;
+    for (int64_t P = 0; P < n; P += cap) {
+        const int64_t lanes = (std::min(cap, n - P) - 1) / sh.H;  // last lane holding a row
+        steps += m + lanes % 64 + (lanes / 64) * (64 + (sh.G > 1 ? 16 : 0));
+    }
+    return steps;
 }
 
 // Workgroups of several wavefronts also pay the LDS hand-over and barriers
@@ -225,16 +254,19 @@ int64_t cyclic_cost(int H, int64_t n, int64_t m) {
 
 // Strip shape for a pair whose shorter series has n points: of the two
 // instantiated shapes of smallest row capacity 64*H*G >= n (restricted to
-// H == force_h when force_h > 0), the cheaper by the cost model ({0,0} if none
-// fits).
+// H == force_h when force_h > 0), the cheaper by the cost model; when no
+// shape holds n rows, the largest one, swept in row passes ({0,0} if force_h
+// matches no shape).
 StripShape pick_strip(int accum, int n, int m, bool banded, int force_h) {
     StripShape shapes[64];
     const int k = strip_shapes(accum, shapes, 64);
-    StripShape best{0, 0};
+    StripShape best{0, 0}, largest{0, 0};
     int64_t best_cost = 0;
     int taken = 0;
-    for (int i = 0; i < k && i < 64 && taken < 2; ++i)
-        if (64 * shapes[i].H * shapes[i].G >= n && (force_h <= 0 || shapes[i].H == force_h)) {
+    for (int i = 0; i < k && i < 64; ++i) {
+        if (force_h > 0 && shapes[i].H != force_h) continue;
+        largest = shapes[i];  // shapes come in increasing capacity
+        if (taken < 2 && 64 * shapes[i].H * shapes[i].G >= n) {
             const int64_t c = strip_cost(shapes[i], n, m, banded);
             if (!best.H || c < best_cost) {
                 best = shapes[i];
@@ -242,7 +274,8 @@ StripShape pick_strip(int accum, int n, int m, bool banded, int force_h) {
             }
             ++taken;
         }
-    return best;
+    }
+    return best.H ? best : largest;
 }
 
 // Cheapest instantiated cyclic block height for the pair (0 if none fits);
@@ -262,14 +295,6 @@ int pick_cyclic(int64_t n, int64_t m, int64_t b, int force_h, int64_t *cost) {
         }
     }
     *cost = best_cost;
-    return best;
-}
-
-int max_strip_rows(int accum) {
-    StripShape shapes[64];
-    const int k = strip_shapes(accum, shapes, 64);
-    int best = 0;
-    for (int i = 0; i < k && i < 64; ++i) best = std::max(best, 64 * shapes[i].H * shapes[i].G);
     return best;
 }
 
@@ -344,6 +369,7 @@ struct dtw_plan_s {
     int dtype = 0, accum = 0, kernel = 0, flags = 0;  // accum: the public dtw_accum
     int32_t nseries = 0;
     void *dev_block = nullptr;  // one allocation holding everything below
+    void *pass_block = nullptr; // row-pass buffers of strip groups with very long pairs
     size_t dev_bytes = 0;
     float *ws = nullptr;
     SeriesSrc *d_src = nullptr;
@@ -394,6 +420,9 @@ int validate_options(const dtw_options *opt) {
 
 // need_all: the dataset is evaluated for all its pairs (N >= 2 needs series
 // and out_condensed); otherwise for a pair list (N >= 1 needs series).
+// Series lengths stay below 2^28 points so that every step and column count of
+// a kernel fits an int.
+constexpr int32_t kMaxSeriesLen = 1 << 28;
 int validate_dataset(const dtw_dataset &d, int idx, bool need_all = true) {
     if (d.N < 0) return fail(DTW_ERR_INVALID_ARG, "dataset %d: N=%d < 0", idx, d.N);
     if (d.N < (need_all ? 2 : 1)) return DTW_OK;
@@ -402,6 +431,9 @@ int validate_dataset(const dtw_dataset &d, int idx, bool need_all = true) {
     if (!d.lengths || !d.offsets) return fail(DTW_ERR_INVALID_ARG, "dataset %d: lengths/offsets is NULL", idx);
     for (int32_t s = 0; s < d.N; ++s) {
         if (d.lengths[s] < 1) return fail(DTW_ERR_INVALID_ARG, "dataset %d: lengths[%d]=%d < 1", idx, s, d.lengths[s]);
+        if (d.lengths[s] > kMaxSeriesLen)
+            return fail(DTW_ERR_UNSUPPORTED, "dataset %d: lengths[%d]=%d exceeds %d points", idx, s, d.lengths[s],
+                        kMaxSeriesLen);
         if (d.offsets[s] < 0) return fail(DTW_ERR_INVALID_ARG, "dataset %d: offsets[%d] < 0", idx, s);
     }
     return DTW_OK;
@@ -410,6 +442,7 @@ int validate_dataset(const dtw_dataset &d, int idx, bool need_all = true) {
 void destroy_plan(dtw_plan p) {
     if (!p) return;
     if (p->dev_block) (void)hipFree(p->dev_block);
+    if (p->pass_block) (void)hipFree(p->pass_block);
     if (p->ev0) (void)hipEventDestroy(p->ev0);
     if (p->ev1) (void)hipEventDestroy(p->ev1);
     if (p->fork_ev) (void)hipEventDestroy(p->fork_ev);
@@ -513,7 +546,7 @@ int autotune(dtw_plan p, const std::vector<WavePair> &wp, std::vector<Choice> &c
         for (const auto &rc_pair : ranked) {
             const Choice c = rc_pair.second;
             const int slots = c.cyclic() ? cyclic_resident(c.H, acc == kAccRebased)
-                                         : strip_resident(acc, StripShape{c.H, c.G}, banded);
+                                         : strip_resident(acc, StripShape{c.H, c.G}, banded, false);
             const int64_t T = std::min<int64_t>(kTuneMaxItems, std::max<int64_t>((int64_t)sample.size(), slots));
             for (int64_t t = 0; t < T; ++t) host[(size_t)t] = make_item(c, wp[sample[(size_t)(t % ns)]]);
             e = hipMemcpy(d_items, host.data(), (size_t)T * sizeof(WaveItem), hipMemcpyHostToDevice);
@@ -521,7 +554,7 @@ int autotune(dtw_plan p, const std::vector<WavePair> &wp, std::vector<Choice> &c
                 return c.cyclic() ? launch_cyclic(c.H, acc == kAccRebased, p->ws, p->d_ser, p->d_ds, d_items,
                                                   (unsigned)T, nullptr, 0, s)
                                   : launch_strip(acc, StripShape{c.H, c.G}, banded, p->ws, p->d_ser, p->d_ds,
-                                                 d_items, (unsigned)T, nullptr, 0, s);
+                                                 d_items, (unsigned)T, nullptr, 0, nullptr, 0, s);
             };
             if (e == hipSuccess && !warmed.count({c, banded})) {  // first launch of an instance loads its code
                 e = run();
@@ -691,17 +724,13 @@ int plan_build(dtw_plan *plan_out, const dtw_dataset *ds, int32_t n_datasets, co
                     st.computed_cells += (int64_t)64 * L * lane_w;
                 }
         } else if (lane_w && full) {
-            const int32_t N = D.N, L = D.lengths[0], b = (lane_w - 1) / 2;
+            const int32_t L = D.lengths[0], b = (lane_w - 1) / 2;
             st.band_cells += npairs * band_cells(L, L, b >= L - 1 ? -1 : b);
-            for (int32_t a = 0; a < N; ++a) {
-                int32_t h = (N - 1) / 2;
-                if (N % 2 == 0 && a < N / 2) h = N / 2;
-                for (int32_t d0 = 1; d0 <= h; d0 += 64) {
-                    const int32_t cnt = std::min(64, h - d0 + 1);
-                    lane_by_w[lane_key].push_back(LaneItem{d, a, d0, cnt, -1});
-                    st.computed_cells += (int64_t)64 * L * lane_w;
-                }
-            }
+            std::vector<LaneItem> &items = lane_by_w[lane_key];
+            lane_cyclic_tiles(D.N, [&](int32_t a, int32_t d0, int32_t cnt) {
+                items.push_back(LaneItem{d, a, d0, cnt, -1});
+                st.computed_cells += (int64_t)64 * L * lane_w;
+            });
         } else if (lane_w) {
             // a part of the condensed matrix: runs of up to 64 consecutive
             // partners j > i of one series i (partner a + d0 + lane, no wrap)
@@ -746,9 +775,8 @@ int plan_build(dtw_plan *plan_out, const dtw_dataset *ds, int32_t n_datasets, co
                                         "dataset %d: pair (%d,%d) (%d x %d points, band %d): no kernel with "
                                         "rows_per_lane=%d fits it",
                                         d, (int)i, (int)j, w.n, w.m, w.b, force_h);
-                        return fail(DTW_ERR_UNSUPPORTED,
-                                    "dataset %d: pair (%d,%d) has both series longer than %d points", d, (int)i,
-                                    (int)j, max_strip_rows(w.acc));
+                        return fail(DTW_ERR_UNSUPPORTED, "dataset %d: pair (%d,%d): no kernel instance fits it", d,
+                                    (int)i, (int)j);
                     }
                     wpairs.push_back(w);
                 }
@@ -851,6 +879,7 @@ int plan_build(dtw_plan *plan_out, const dtw_dataset *ds, int32_t n_datasets, co
     using Kind = std::tuple<int, int, bool, int>;  // H, G, banded, AccMode
     std::map<Kind, std::vector<std::pair<int64_t, WaveItem>>> wave_by_kind;
     std::map<Kind, std::pair<int64_t, int64_t>> cells_by_kind;  // admissible, swept
+    std::map<Kind, std::pair<int64_t, int64_t>> extent_by_kind;  // longest rows, cols
     for (size_t k = 0; k < wpairs.size(); ++k) {
         const Choice c = choice[k];
         const WavePair &w = wpairs[k];
@@ -862,6 +891,9 @@ int plan_build(dtw_plan *plan_out, const dtw_dataset *ds, int32_t n_datasets, co
         auto &cells = cells_by_kind[kind];
         cells.first += band_cells(w.n, w.m, w.b);
         cells.second += swept;
+        auto &ext = extent_by_kind[kind];
+        ext.first = std::max<int64_t>(ext.first, c.cyclic() ? w.m : w.n);
+        ext.second = std::max<int64_t>(ext.second, c.cyclic() ? w.n : w.m);
     }
     std::vector<decltype(wave_by_kind)::iterator> order;
     for (auto it = wave_by_kind.begin(); it != wave_by_kind.end(); ++it) {
@@ -883,9 +915,10 @@ int plan_build(dtw_plan *plan_out, const dtw_dataset *ds, int32_t n_datasets, co
         }
         const StripShape sh{std::get<0>(it->first), std::get<1>(it->first)};
         const auto &cells = cells_by_kind[it->first];
+        const auto &ext = extent_by_kind[it->first];
         p->wave_groups.push_back(WaveGroup{sh, std::get<2>(it->first), std::get<3>(it->first),
                                            (int64_t)wave_items.size(), (int64_t)v.size(), 0, cells.first,
-                                           cells.second});
+                                           cells.second, ext.first, ext.second});
         for (auto &e2 : v) wave_items.push_back(e2.second);
     }
     if (p->wave_groups.size() > (size_t)kMaxQueues) {
@@ -902,10 +935,39 @@ int plan_build(dtw_plan *plan_out, const dtw_dataset *ds, int32_t n_datasets, co
     const bool use_queue = !(flags & DTW_FLAG_NO_QUEUE) && !p->wave_groups.empty();
     p->n_queue = use_queue ? (int)p->wave_groups.size() : 0;
     p->d_queue = p->n_queue ? reinterpret_cast<unsigned *>(base + o_queue) : nullptr;
+    auto needs_passes = [](const WaveGroup &g) {
+        return g.shape.G > 0 && g.max_rows > (int64_t)64 * g.shape.H * g.shape.G;
+    };
     if (use_queue)  // grid of each launch: the workgroups the device holds at once
         for (WaveGroup &g : p->wave_groups)
             g.slots = g.shape.G == 0 ? cyclic_resident(g.shape.H, g.acc == kAccRebased)
-                                     : strip_resident(g.acc, g.shape, g.banded);
+                                     : strip_resident(g.acc, g.shape, g.banded, needs_passes(g));
+    // Row-pass buffers: one row of the longest swept series per workgroup of
+    // every strip group holding a pair of more than 64*H*G rows.
+    {
+        size_t pass_bytes = 0;
+        std::vector<size_t> pass_off(p->wave_groups.size(), 0);
+        for (size_t k = 0; k < p->wave_groups.size(); ++k) {
+            const WaveGroup &g = p->wave_groups[k];
+            if (!needs_passes(g)) continue;
+            const int grid = strip_grid((unsigned)g.count, use_queue ? p->d_queue : nullptr, g.slots);
+            pass_off[k] = pass_bytes + 1;  // 0 = none
+            pass_bytes = align_up(pass_bytes + (size_t)grid * (size_t)g.max_cols * strip_cell_bytes(g.acc), 256);
+        }
+        if (pass_bytes) {
+            if ((e = hipMalloc(&p->pass_block, pass_bytes)) != hipSuccess) {
+                destroy_plan(p);
+                return fail(DTW_ERR_OUT_OF_MEMORY, "hipMalloc(%zu bytes) for row passes: %s", pass_bytes,
+                            hipGetErrorString(e));
+            }
+            for (size_t k = 0; k < p->wave_groups.size(); ++k)
+                if (pass_off[k]) {
+                    p->wave_groups[k].pass_buf = static_cast<char *>(p->pass_block) + (pass_off[k] - 1);
+                    p->wave_groups[k].pass_stride = p->wave_groups[k].max_cols;
+                }
+            st.workspace_bytes += (int64_t)pass_bytes;
+        }
+    }
     st.n_launches = (p->nseries > 0 ? 1 : 0) + (use_queue ? 1 : 0) +
                     (int32_t)(p->lane_groups.size() + p->wave_groups.size());
     p->stats = st;
@@ -1115,11 +1177,7 @@ int noalloc_run(const dtw_dataset &d, const dtw_options &o) {
                     kLaneMaxW);
     int64_t n_lane = 0;
     const int64_t n_pairs = (int64_t)N * (N - 1) / 2;
-    if (lane_w)
-        for (int32_t a = 0; a < N; ++a) {
-            const int32_t h = (N % 2 == 0 && a < N / 2) ? N / 2 : (N - 1) / 2;
-            n_lane += (h + 63) / 64;
-        }
+    if (lane_w) lane_cyclic_tiles(N, [&](int32_t, int32_t, int32_t) { ++n_lane; });
     const size_t o_ws = 0;
     size_t off = align_up(ws_floats * sizeof(float), 256);
     const size_t o_src = off;
@@ -1162,10 +1220,7 @@ int noalloc_run(const dtw_dataset &d, const dtw_options &o) {
     if (lane_w) {
         LaneItem *it = reinterpret_cast<LaneItem *>(h + (o_items - o_src));
         int64_t k = 0;
-        for (int32_t a = 0; a < N; ++a) {
-            const int32_t hh = (N % 2 == 0 && a < N / 2) ? N / 2 : (N - 1) / 2;
-            for (int32_t d0 = 1; d0 <= hh; d0 += 64) it[k++] = LaneItem{0, a, d0, std::min(64, hh - d0 + 1), -1};
-        }
+        lane_cyclic_tiles(N, [&](int32_t a, int32_t d0, int32_t cnt) { it[k++] = LaneItem{0, a, d0, cnt, -1}; });
     } else {
         NoAllocRec *rec = reinterpret_cast<NoAllocRec *>(h + o_sort);
         int64_t k = 0;
@@ -1180,6 +1235,11 @@ int noalloc_run(const dtw_dataset &d, const dtw_options &o) {
                 if (!c.H)
                     return fail(DTW_ERR_UNSUPPORTED, "pair (%d,%d) (%d x %d points, band %d): no kernel fits it", i,
                                 j, w.n, w.m, w.b);
+                if (!c.cyclic() && w.n > 64 * c.H * c.G)
+                    return fail(DTW_ERR_UNSUPPORTED,
+                                "pair (%d,%d): a shorter series of %d points is swept in row passes, whose buffer "
+                                "the allocation-free entry point does not hold",
+                                i, j, w.n);
                 const uint32_t banded = (c.cyclic() || w.b >= 0) ? 1u : 0u;
                 rec[k] = NoAllocRec{(((uint32_t)c.H * 32u + (uint32_t)c.G) * 2u + banded) * 4u + (uint32_t)w.acc,
                                     choice_cost(c, w), make_item(c, w)};
@@ -1242,7 +1302,8 @@ int noalloc_run(const dtw_dataset &d, const dtw_options &o) {
         else
             e = launch_strip(acc, StripShape{H, G}, banded != 0, ws, dser, dds, ditems + groups[g].begin,
                              (unsigned)groups[g].count, queue,
-                             use_queue ? strip_resident(acc, StripShape{H, G}, banded != 0) : 0, st);
+                             use_queue ? strip_resident(acc, StripShape{H, G}, banded != 0, false) : 0, nullptr, 0,
+                             st);
         if (e != hipSuccess) return hip_fail(e, "wavefront kernel launch");
     }
     return DTW_OK;
@@ -1309,7 +1370,7 @@ int dtw_plan_execute(dtw_plan p, void *stream) {
                               (unsigned)g.count, queue, g.slots, gs);
         else
             e = launch_strip(g.acc, g.shape, g.banded, p->ws, p->d_ser, p->d_ds, p->d_wave + g.begin,
-                             (unsigned)g.count, queue, g.slots, gs);
+                             (unsigned)g.count, queue, g.slots, g.pass_buf, g.pass_stride, gs);
         if (e != hipSuccess) what = "wavefront kernel launch";
     }
     const hipError_t e_launch = e;
@@ -1361,11 +1422,13 @@ int dtw_plan_describe(dtw_plan p, char *buf, int64_t size, int64_t *needed) {
         const WaveGroup &g = p->wave_groups[k];
         snprintf(t, sizeof t,
                  "%s{\"kernel\": \"%s\", \"accum\": \"%s\", \"banded\": %s, \"items\": %lld, \"grid\": %lld, "
-                 "\"band_cells\": %lld, \"swept_cells\": %lld}",
+                 "\"band_cells\": %lld, \"swept_cells\": %lld, \"max_row_passes\": %lld}",
                  k ? ", " : "", choice_name(Choice{g.shape.H, g.shape.G}).c_str(), acc_name(g.acc),
                  g.banded ? "true" : "false",
                  (long long)g.count, (long long)(p->n_queue && g.slots > 0 ? std::min<int64_t>(g.slots, g.count) : g.count),
-                 (long long)g.band_cells, (long long)g.swept_cells);
+                 (long long)g.band_cells, (long long)g.swept_cells,
+                 (long long)(g.shape.G ? (g.max_rows + 64LL * g.shape.H * g.shape.G - 1) / (64LL * g.shape.H * g.shape.G)
+                                       : 1));
         j += t;
     }
     j += "], \"tuned\": [";

@@ -1,74 +1,15 @@
-// Internal layout shared by the host planner (dtw_api.hip) and the kernel
+// Kernel launchers shared by the host planner (dtw_api.hip) and the kernel
 // sources (dtw_stage.hip, dtw_lane.hip, dtw_strip.hip, dtw_cyclic.hip,
-// dtw_cluster.hip, dtw_path.hip).  Not part of the public ABI.
+// dtw_cluster.hip, dtw_path.hip); the data layout is in dtw_layout.h.  Not
+// part of the public ABI.
 #pragma once
+
+#include "dtw_layout.h"
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 namespace dtwmi {
-
-// Padding (in FP32 elements) written before and after every staged series.
-// Pad cells hold +inf, so a read of y outside [0, m) yields an inadmissible
-// (+inf) local cost without any branch.  Kernels rely on:
-//   lane-band kernel: reads y[i-B .. i+B] with B <= 63, x[0 .. L+7];
-//   wavefront kernels: clamp column reads into [-1, m].
-constexpr int kPad = 128;
-constexpr int kLaneMaxW = 127;   // widest band (2*B+1) of the lane-band kernel
-
-// Accumulation of a kernel instance (the public dtw_accum AUTO resolves to
-// kAccPlain or kAccRebased per pair):
-//   kAccPlain:   FP32 sub, min3, fused multiply-add per cell;
-//   kAccKahan:   FP32 with a compensation term carried per cell;
-//   kAccF64:     the recurrence in FP64, rounded once at the end;
-//   kAccRebased: the plain FP32 cell, every lane keeping its values relative
-//                to a running base of its own that it renormalises every few
-//                steps (rounding relative to the small stored values).
-enum AccMode { kAccPlain = 0, kAccKahan = 1, kAccF64 = 2, kAccRebased = 3 };
-
-
-struct SeriesSrc {     // where a series lives in the caller's buffer
-    const void *base;  // device pointer of the dataset buffer
-    int64_t off;       // element offset
-    int32_t len;
-    int32_t dtype;     // dtw_dtype
-};
-
-struct SeriesInfo {    // where a series lives in the staged FP32 workspace
-    int64_t pstart;    // index of element 0 (16-byte aligned); pads at [-kPad, 0) and [len, len+kPad)
-    int32_t len;
-    int32_t pad_;
-};
-
-struct DatasetInfo {
-    float *out;        // condensed output of this dataset
-    int32_t N;
-    int32_t window;    // as given (< 0 = none)
-    int32_t L;         // common length if all series are equal, else -1
-    int32_t series_base;  // global index of the dataset's first series
-};
-
-// Lane-band work item: one wavefront evaluates, for lane < cnt, the pair of
-// series a and partner b written to output slot k:
-//   list < 0:  b = (a + d0 + lane) mod N, k = condensed index of (a, b);
-//   list >= 0: (b, k) = partners[list + lane] (explicit pair lists).
-// All series of the dataset have length L.
-struct LaneItem {
-    int32_t ds, a, d0, cnt;
-    int64_t list;
-};
-struct LanePartner {
-    int32_t b, pad_;
-    int64_t slot;
-};
-
-// Wavefront work item: one pair; `rows` is the series spread over the lanes,
-// `cols` the one swept step by step; the result goes to out[slot] of the
-// dataset (the condensed index for all-pairs plans).
-struct WaveItem {
-    int32_t ds, rows, cols, band;  // band = max(w, |n-m|), or -1 for none
-    int64_t slot;
-};
 
 // Kernel launchers (one kernel source each).  All asynchronous on `stream`.
 // Wavefront launchers take the item count and a queue counter: with queue == nullptr
@@ -98,10 +39,17 @@ struct StripShape {
 // Instantiated shapes for an accumulation mode (AccMode), in increasing row capacity;
 // returns their number (writes at most max_out of them).
 int strip_shapes(int accum, StripShape *out, int max_out);
-int strip_resident(int accum, StripShape shape, bool banded);
+// Workgroups of an instance the device holds at once (passes: the row-pass form).
+int strip_resident(int accum, StripShape shape, bool banded, bool passes);
+// Pairs whose shorter series exceeds 64*H*G rows are swept in row passes; they
+// need pass_buf: pass_stride (>= the longest swept series) values of the
+// mode's cell type (strip_cell_bytes) per workgroup of the launch
+// (strip_grid workgroups), else nullptr.
 hipError_t launch_strip(int accum, StripShape shape, bool banded, const float *ws, const SeriesInfo *ser,
                         const DatasetInfo *dsi, const WaveItem *items, unsigned n_items, unsigned *queue, int slots,
-                        hipStream_t stream);
+                        void *pass_buf, int64_t pass_stride, hipStream_t stream);
+int strip_grid(unsigned n_items, unsigned *queue, int slots);  // workgroups of a strip launch
+constexpr int strip_cell_bytes(int accum) { return accum == kAccF64 || accum == kAccKahan ? 8 : 4; }
 // Cyclic banded strips (kAccPlain or, with rebased, kAccRebased; window
 // required): H rows per block, blocks cycling over the 64 lanes of one
 // wavefront; needs 64(H+1) >= 2b+H whenever the pair has more than 64 blocks.

@@ -104,19 +104,26 @@ constexpr int kLaneRebaseRows = 32;
 
 // Lane-band items have equal cost, so the kernel takes one item per workgroup
 // (hardware dispatch); an item loop would only add registers to this kernel.
+// Workgroups go to the 8 XCDs of the device in turn, so workgroup w takes item
+// (w mod 8) * ceil(n/8) + w / 8: each XCD works through one contiguous eighth
+// of the item list, whose tiles share row series in that XCD's L2 (any order
+// is correct; this one only keeps the reads local).
 template <int W, bool RB>
 __global__ __launch_bounds__(64) void k_lane(const float *__restrict__ ws, const SeriesInfo *__restrict__ ser,
                                              const DatasetInfo *__restrict__ dsi,
                                              const LaneItem *__restrict__ items,
-                                             const LanePartner *__restrict__ partners) {
+                                             const LanePartner *__restrict__ partners, unsigned n_items) {
     constexpr int B = (W - 1) / 2, R = kLaneRows, C = kLaneChunk;
-    const LaneItem it = items[blockIdx.x];
+    const unsigned per_xcd = (n_items + 7) / 8;
+    const unsigned idx = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    if (idx >= n_items) return;
+    const LaneItem it = items[idx];
     const DatasetInfo D = dsi[it.ds];
     const int lane = threadIdx.x;
     const bool valid = lane < it.cnt;
     int bl;
     int64_t slot;
-    if (it.list < 0) {  // all pairs: cyclic partner tiling, condensed output
+    if (it.list < 0) {  // all pairs: partner (a + d0 + lane) mod N, condensed output
         bl = it.a + it.d0 + lane;
         bl = bl >= D.N ? bl - D.N : bl;
         const int a = it.a < bl ? it.a : bl, b = it.a < bl ? bl : it.a;
@@ -186,7 +193,8 @@ using LaneFn = hipError_t (*)(const float *, const SeriesInfo *, const DatasetIn
 template <bool RB, int I>
 hipError_t lane_launcher(const float *ws, const SeriesInfo *ser, const DatasetInfo *dsi, const LaneItem *items,
                          const LanePartner *partners, unsigned n, hipStream_t st) {
-    hipLaunchKernelGGL((k_lane<2 * I + 1, RB>), dim3(n), dim3(64), 0, st, ws, ser, dsi, items, partners);
+    hipLaunchKernelGGL((k_lane<2 * I + 1, RB>), dim3(8 * ((n + 7) / 8)), dim3(64), 0, st, ws, ser, dsi, items,
+                       partners, n);
     return hipGetLastError();
 }
 

@@ -48,7 +48,12 @@ struct AccPlain {  // FP32: sub, min3, fused multiply-add
 // steps the base moves up to the smallest value on the wavefront's current
 // frontier -- its lanes' current cells, the boundary values they hold and,
 // for a wavefront after the first, every value of the LDS ring from the
-// wavefront above and the base that one last posted.  Every path to a cell
+// wavefront above and the floor that one last posted (its base, or +inf once
+// its whole frontier has left the window: without that, a wavefront below
+// would stay capped at a base frozen when the window moved past the rows
+// above, and its sums would round like plain ones); in a row pass after the
+// first, the first wavefront also holds the smallest value of the row above
+// the pass.  Every path to a cell
 // computed later passes through that frontier and local costs are never
 // negative, so the base stays below every value computed afterwards: stored
 // values lie between 0 and the true cost, and each fused add rounds relative
@@ -70,28 +75,37 @@ constexpr int kRebaseSteps2 = 16;
 // Renormalise a wavefront: the base moves up by the smallest of the H cells of
 // every lane and `held` (the lane's other frontier values, relative to the
 // base); returns the shift applied (the difference of the new and the old base
-// as computed, subtracted from every stored value).  All +inf: no shift.
+// as computed, subtracted from every stored value).  All +inf: no shift, and
+// `floor` (the absolute lower bound of every value the wavefront computes from
+// now on, which it posts for the wavefront below) becomes +inf -- a frontier
+// of +inf only ever produces +inf -- else it is the new base.
 template <int H>
-__device__ __forceinline__ float rebase_wave(float (&A)[H], float held, float &base) {
+__device__ __forceinline__ float rebase_wave(float (&A)[H], float held, float &base, float &floor) {
     float mn = held;
 #pragma unroll
     for (int h = 0; h < H; ++h) mn = fminf(mn, A[h]);
     mn = wave_min(mn);
-    const float nb = base + (mn < kInf ? mn : 0.0f);
+    const bool live = mn < kInf;
+    const float nb = base + (live ? mn : 0.0f);
     const float d = nb - base;
 #pragma unroll
     for (int h = 0; h < H; ++h) A[h] -= d;
     base = nb;
+    floor = live ? nb : kInf;
     return d;
 }
 
-// Kahan-compensated FP32: each cell carries (s, c) with the true value close
-// to s - c.  The min compares the running sums s (ties prefer diag, then up,
-// then left) and takes the compensation of the chosen predecessor; the local
-// cost is then added with Kahan's compensated step.  An unreachable cell (s =
-// +inf) gets c = NaN from inf - inf; that is harmless: a reachable cell has a
-// finite predecessor, fminf ignores quiet NaNs and NaN never compares equal,
-// so such a c is never selected.
+// Kahan-compensated FP32: each cell carries (s, c) with the true value close to
+// s - c and |c| about half an ulp of s at most.  The predecessor is the
+// smallest (s, -c) in lexicographic order: the smallest running sum s and,
+// among equal sums, the largest compensation, i.e. the smallest true value
+// (sums differing by an ulp or more are ordered by s alone).  Ties of s are
+// common where local costs fall below an ulp of the cumulative cost and are
+// absorbed into c, so taking the first tied predecessor would add up to an ulp
+// per such cell, a bias that grows with the path.  The local cost is then added
+// with Kahan's compensated step.  An unreachable cell (s = +inf) gets c = NaN
+// from inf - inf; that is harmless: a reachable cell has a finite predecessor,
+// whose s is the minimum, so the c of an unreachable one is masked out.
 struct KahanCell {
     float s, c;
 };
@@ -103,8 +117,10 @@ struct AccKahan {
         const float d = xe - yv;
         const float q = d * d;
         const float p = min3f(diag.s, up.s, left.s);
-        const float c1 = (p == up.s) ? up.c : left.c;
-        const float cs = (p == diag.s) ? diag.c : c1;
+        const float cd = (p == diag.s) ? diag.c : -kInf;
+        const float cu = (p == up.s) ? up.c : -kInf;
+        const float cl = (p == left.s) ? left.c : -kInf;
+        const float cs = fmaxf(fmaxf(cd, cu), cl);
         const float yk = q - cs;
         const float t = p + yk;
         return {t, (t - p) - yk};
@@ -197,14 +213,42 @@ __device__ __forceinline__ void strip_step(int c, float yv, const XT &x, const t
     }
 }
 
-template <class ACC, int H, int G, bool BANDED>
+// A value of the pass buffer as another wavefront of the workgroup last wrote
+// it: an agent-scope atomic load, served by L2 (no stale cache line of an
+// earlier pass, and never a scalar load).
+__device__ __forceinline__ float pass_load(const float *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double pass_load(const double *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ KahanCell pass_load(const KahanCell *p) {
+    const unsigned long long v = __hip_atomic_load(reinterpret_cast<const unsigned long long *>(p), __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+    return {__uint_as_float(static_cast<unsigned>(v)), __uint_as_float(static_cast<unsigned>(v >> 32))};
+}
+
+// Pairs whose shorter series has more rows than the workgroup holds (n >
+// 64HG) are swept in row passes of 64HG rows: pass p covers rows [pR, pR+R)
+// over every column, with lane 0 of wavefront 0 reading the row above, pR-1,
+// from a global buffer of the workgroup (m values) that the last lane of the
+// last wavefront of pass p-1 wrote, and writing its own last row over it.  At
+// every column the read comes dozens of steps before the write (the skew of
+// the workgroup's lanes), in program order for one wavefront and across
+// barriers for several; between passes a fence and a barrier make the row
+// visible.  Values in the buffer are absolute (plus the base, for rebased
+// sums).  PASSES = false instantiates the single-pass sweep alone (no buffer;
+// every pair fits), which needs fewer registers.
+template <class ACC, int H, int G, bool BANDED, bool PASSES>
 __device__ __forceinline__ void strip_item(const WaveItem it, const float *__restrict__ ws,
                                            const SeriesInfo *__restrict__ ser, const DatasetInfo *__restrict__ dsi,
-                                           typename ACC::T (*ring)[kRing], float *bound) {
+                                           typename ACC::T (*ring)[kRing], float *bound,
+                                           typename ACC::T *__restrict__ pbuf) {
     using T = typename ACC::T;
     constexpr bool EVENTS = BANDED && H <= 32;  // wider strips test every cell
     constexpr bool PERCELL = BANDED && !EVENTS;
     constexpr int D = G > 1 ? kEpoch : 0;
+    constexpr int CAP = 64 * H * G;  // rows of one pass
     typedef typename XVec<H>::T xvec;
 
     const int lane = item_lane(it.ds) & 63;
@@ -215,124 +259,171 @@ __device__ __forceinline__ void strip_item(const WaveItem it, const float *__res
     const int n = sr.len, m = sc.len, band = it.band;
     const float *__restrict__ xp = ws + sr.pstart;
     const float *__restrict__ yp = ws + sc.pstart;
-    const int rbase = (wave * 64 + lane) * H;
     const int skew = lane + wave * (64 + D);  // column = s - skew
-    const int Lf = (n - 1) / H, wf = Lf >> 6, lf = Lf & 63, hf = (n - 1) - Lf * H;
-    const int sfinal = (m - 1) + lf + wf * (64 + D);  // step computing cell (n-1, m-1)
+    const int npass = PASSES ? (n + CAP - 1) / CAP : 1;
 
-    float xa[H];
+    for (int pass = 0; pass < npass; ++pass) {
+        const int P = pass * CAP;  // first row of the pass
+        const bool last = !PASSES || pass == npass - 1;
+        const bool top = PASSES && pass > 0 && wave == 0;  // lane 0 reads the row above from pbuf
+        const int rbase = P + (wave * 64 + lane) * H;
+        const int rl = (last ? n - 1 : P + CAP - 1) - P;  // the pass's last row, local
+        const int Lf = rl / H, wf = Lf >> 6, lf = Lf & 63, hf = rl - Lf * H;
+        const int sfinal = (m - 1) + lf + wf * (64 + D);  // step computing (last row, m-1)
+
+        float xa[H];
 #pragma unroll
-    for (int h = 0; h < H; ++h) {
-        const int r = rbase + h;
-        const float v = xp[r < n ? r : n - 1];
-        xa[h] = r < n ? v : 0.0f;  // rows past n never feed row n-1
-    }
-    xvec xr, x;
-    T A[H], Bv[H];
+        for (int h = 0; h < H; ++h) {
+            const int r = rbase + h;
+            const float v = xp[r < n ? r : n - 1];
+            xa[h] = r < n ? v : 0.0f;  // rows past n never feed row n-1
+        }
+        xvec xr, x;
+        T A[H], Bv[H];
 #pragma unroll
-    for (int h = 0; h < H; ++h) {
-        const int r = rbase + h;
-        xr[h] = xa[h];
-        x[h] = (!EVENTS || (r < n && r - band <= 0)) ? xa[h] : kBig;
-        A[h] = ACC::inf();
-        Bv[h] = ACC::inf();
-    }
-    BandEvents ev;
-    if constexpr (EVENTS) ev.init(rbase, skew, band);
-    if constexpr (G > 1) {
-        for (int k = threadIdx.x; k < (G - 1) * kRing; k += 64 * G) ring[k / kRing][k % kRing] = ACC::inf();
+        for (int h = 0; h < H; ++h) {
+            const int r = rbase + h;
+            xr[h] = xa[h];
+            x[h] = (!EVENTS || (r < n && r - band <= 0)) ? xa[h] : kBig;
+            A[h] = ACC::inf();
+            Bv[h] = ACC::inf();
+        }
+        BandEvents ev;
+        if constexpr (EVENTS) ev.init(rbase, skew, band);
+        if constexpr (G > 1) {
+            for (int k = threadIdx.x; k < (G - 1) * kRing; k += 64 * G) ring[k / kRing][k % kRing] = ACC::inf();
+            if constexpr (kRebased<ACC>) {
+                if (threadIdx.x < G) bound[threadIdx.x] = 0.0f;  // the trivial lower bound
+            }
+            __syncthreads();
+        }
+        float base = 0.0f;     // rebased accumulation only: the wavefront's base
+        float top_min = kInf;  // rebased passes after the first: the smallest value of the row above
         if constexpr (kRebased<ACC>) {
-            if (threadIdx.x < G) bound[threadIdx.x] = 0.0f;  // the trivial lower bound
-        }
-        __syncthreads();
-    }
-    T up_in = ACC::inf();
-    T diag_in = (lane == 0 && wave == 0) ? ACC::zero() : ACC::inf();  // c(0,0) of the 1-based recurrence
-    float base = 0.0f;  // rebased accumulation only: the wavefront's base
-
-    // y of column s - skew; the +inf pads cover the columns a single wavefront
-    // reads ([-63, m+64]), later wavefronts clamp into [-1, m]
-    auto yat = [&](int s) {
-        const int c = s - skew;
-        if constexpr (G == 1) return yp[c];
-        return yp[c < -1 ? -1 : (c > m ? m : c)];
-    };
-    // value handed to lane 0 of this wavefront (LDS ring for wavefronts after the first)
-    auto boundary = [&](int s) -> T {
-        if constexpr (G > 1) {
-            if (wave > 0) {
-                if constexpr (kRebased<ACC>) return ring[wave - 1][(s - skew) & (kRing - 1)] - base;
-                return ring[wave - 1][(s - skew) & (kRing - 1)];
+            if (top) {
+                for (int c = lane; c < m; c += 64) top_min = fminf(top_min, pass_load(pbuf + c));
+                top_min = wave_min(top_min);
             }
         }
-        return ACC::inf();
-    };
-    auto publish = [&](int s, const T &bottom) {
-        if constexpr (G > 1) {
-            if (lane == 63 && wave < G - 1) {
-                if constexpr (kRebased<ACC>)
-                    ring[wave][(s - skew) & (kRing - 1)] = bottom + base;
-                else
-                    ring[wave][(s - skew) & (kRing - 1)] = bottom;
+        // value of the row above at column c (lane 0 of wavefront 0, passes after the first)
+        auto top_at = [&](int c) -> T {
+            if constexpr (PASSES) {
+                if (c < 0 || c >= m) return ACC::inf();
+                if constexpr (kRebased<ACC>) return pass_load(pbuf + c) - base;
+                return pass_load(pbuf + c);
+            }
+            return ACC::inf();
+        };
+        T up_in = ACC::inf();
+        if (top) up_in = lane == 0 ? top_at(0) : ACC::inf();
+        T diag_in = (lane == 0 && wave == 0 && pass == 0) ? ACC::zero() : ACC::inf();  // c(0,0), 1-based
+
+        // y of column s - skew; the +inf pads cover the columns a single wavefront
+        // reads ([-63, m+64]), later wavefronts clamp into [-1, m]
+        auto yat = [&](int s) {
+            const int c = s - skew;
+            if constexpr (G == 1) return yp[c];
+            return yp[c < -1 ? -1 : (c > m ? m : c)];
+        };
+        // value handed to lane 0 of this wavefront: the LDS ring for wavefronts after
+        // the first, the row above from pbuf for the first wavefront of a later pass
+        // (column s for its lane 0, whose skew is 0)
+        auto boundary = [&](int s) -> T {
+            if constexpr (G > 1) {
+                if (wave > 0) {
+                    if constexpr (kRebased<ACC>) return ring[wave - 1][(s - skew) & (kRing - 1)] - base;
+                    return ring[wave - 1][(s - skew) & (kRing - 1)];
+                }
+            }
+            if (top) return top_at(s);
+            return ACC::inf();
+        };
+        auto publish = [&](int s, const T &bottom) {
+            if constexpr (G > 1) {
+                if (lane == 63 && wave < G - 1) {
+                    if constexpr (kRebased<ACC>)
+                        ring[wave][(s - skew) & (kRing - 1)] = bottom + base;
+                    else
+                        ring[wave][(s - skew) & (kRing - 1)] = bottom;
+                }
+            }
+            if (PASSES && !last && lane == 63 && wave == G - 1) {  // the pass's last row, for the next pass
+                const int c = s - skew;
+                if (c >= 0 && c < m) {
+                    if constexpr (kRebased<ACC>)
+                        pbuf[c] = bottom + base;
+                    else
+                        pbuf[c] = bottom;
+                }
+            }
+        };
+
+        // Every wavefront of the workgroup runs steps 0..sfinal (a uniform count,
+        // so all reach the same barriers); the result is read after the last step.
+        float y0 = yat(0), y1 = yat(1);
+        int s = 0;
+        for (; s + 2 <= sfinal + 1; s += 2) {
+            const float y2 = yat(s + 2), y3 = yat(s + 3);
+            const T b1 = boundary(s + 1), b2 = boundary(s + 2);
+            if constexpr (EVENTS) ev.step<H>(s, x, xr);
+            strip_step<ACC, H, PERCELL>(s - skew, y0, x, A, Bv, up_in, diag_in, rbase, band);
+            {
+                const T recv = lane_shift_down(Bv[H - 1], b1);
+                publish(s, Bv[H - 1]);
+                diag_in = up_in;
+                up_in = recv;
+            }
+            if constexpr (EVENTS) ev.step<H>(s + 1, x, xr);
+            strip_step<ACC, H, PERCELL>(s + 1 - skew, y1, x, Bv, A, up_in, diag_in, rbase, band);
+            {
+                const T recv = lane_shift_down(A[H - 1], b2);
+                publish(s + 1, A[H - 1]);
+                diag_in = up_in;
+                up_in = recv;
+            }
+            if constexpr (kRebased<ACC>) {
+                if ((s + 2) % kRebaseSteps == 0) {
+                    float held = fminf(up_in, diag_in);
+                    if constexpr (G > 1) {
+                        if (wave > 0) held = fminf(held, fminf(ring[wave - 1][lane], bound[wave - 1]) - base);
+                    }
+                    if (top) held = fminf(held, top_min - base);
+                    float floor;
+                    const float d = rebase_wave<H>(A, held, base, floor);
+                    up_in -= d;
+                    diag_in -= d;
+                    if constexpr (G > 1) {
+                        if (lane == 0) bound[wave] = floor;
+                    }
+                }
+            }
+            y0 = y2;
+            y1 = y3;
+            if constexpr (G > 1) {
+                if ((s + 2) % kEpoch == 0) __syncthreads();
             }
         }
-    };
-
-    // Every wavefront of the workgroup runs steps 0..sfinal (a uniform count,
-    // so all reach the same barriers); the result is read after the last step.
-    float y0 = yat(0), y1 = yat(1);
-    int s = 0;
-    for (; s + 2 <= sfinal + 1; s += 2) {
-        const float y2 = yat(s + 2), y3 = yat(s + 3);
-        if constexpr (EVENTS) ev.step<H>(s, x, xr);
-        strip_step<ACC, H, PERCELL>(s - skew, y0, x, A, Bv, up_in, diag_in, rbase, band);
-        {
-            const T recv = lane_shift_down(Bv[H - 1], boundary(s + 1));
+        T res;
+        if (s <= sfinal) {  // one step left (s == sfinal)
+            if constexpr (EVENTS) ev.step<H>(s, x, xr);
+            strip_step<ACC, H, PERCELL>(s - skew, y0, x, A, Bv, up_in, diag_in, rbase, band);
             publish(s, Bv[H - 1]);
-            diag_in = up_in;
-            up_in = recv;
+            res = pick<H>(Bv, hf);
+        } else {
+            res = pick<H>(A, hf);
         }
-        if constexpr (EVENTS) ev.step<H>(s + 1, x, xr);
-        strip_step<ACC, H, PERCELL>(s + 1 - skew, y1, x, Bv, A, up_in, diag_in, rbase, band);
-        {
-            const T recv = lane_shift_down(A[H - 1], boundary(s + 2));
-            publish(s + 1, A[H - 1]);
-            diag_in = up_in;
-            up_in = recv;
+        if (PASSES && !last) {
+            // the row is written: make it visible to every wavefront before the next pass
+            __threadfence();
+            __syncthreads();
+            continue;
         }
-        if constexpr (kRebased<ACC>) {
-            if ((s + 2) % kRebaseSteps == 0) {
-                float held = fminf(up_in, diag_in);
-                if constexpr (G > 1) {
-                    if (wave > 0) held = fminf(held, fminf(ring[wave - 1][lane], bound[wave - 1]) - base);
-                }
-                const float d = rebase_wave<H>(A, held, base);
-                up_in -= d;
-                diag_in -= d;
-                if constexpr (G > 1) {
-                    if (lane == 0) bound[wave] = base;
-                }
-            }
+        if (wave == wf && lane == lf) {
+            if constexpr (kRebased<ACC>)
+                DI.out[it.slot] = res + base;
+            else
+                DI.out[it.slot] = ACC::result(res);
         }
-        y0 = y2;
-        y1 = y3;
-        if constexpr (G > 1) {
-            if ((s + 2) % kEpoch == 0) __syncthreads();
-        }
-    }
-    T res;
-    if (s <= sfinal) {  // one step left (s == sfinal)
-        if constexpr (EVENTS) ev.step<H>(s, x, xr);
-        strip_step<ACC, H, PERCELL>(s - skew, y0, x, A, Bv, up_in, diag_in, rbase, band);
-        res = pick<H>(Bv, hf);
-    } else {
-        res = pick<H>(A, hf);
-    }
-    if (wave == wf && lane == lf) {
-        if constexpr (kRebased<ACC>)
-            DI.out[it.slot] = res + base;
-        else
-            DI.out[it.slot] = ACC::result(res);
     }
 }
 
@@ -452,12 +543,13 @@ __device__ __forceinline__ void strip2_item(const WaveItem it, const float *__re
                 if constexpr (G > 1) {
                     if (wave > 0) held = fminf(held, fminf(ring[wave - 1][lane], bound[wave - 1]) - base);
                 }
-                const float d = rebase_wave<H>(A, held, base);
+                float floor;
+                const float d = rebase_wave<H>(A, held, base, floor);
                 recv0 -= d;
                 recv1 -= d;
                 prev1 -= d;
                 if constexpr (G > 1) {
-                    if (lane == 0) bound[wave] = base;
+                    if (lane == 0) bound[wave] = floor;
                 }
             }
         }
@@ -475,11 +567,13 @@ __device__ __forceinline__ void strip2_item(const WaveItem it, const float *__re
     }
 }
 
-template <class ACC, int H, int G, bool BANDED>
+// PASSES: pairs with more rows than 64*H*G may occur, swept in row passes
+// through pass_buf, pass_stride values of ACC::T per workgroup (blockIdx.x).
+template <class ACC, int H, int G, bool BANDED, bool PASSES>
 __global__ __launch_bounds__(64 * G) void k_strip(const float *__restrict__ ws, const SeriesInfo *__restrict__ ser,
                                                   const DatasetInfo *__restrict__ dsi,
                                                   const WaveItem *__restrict__ items, unsigned *__restrict__ queue,
-                                                  unsigned n_items) {
+                                                  unsigned n_items, void *pass_buf, int64_t pass_stride) {
     __shared__ typename ACC::T ring[G > 1 ? G - 1 : 1][kRing];
     __shared__ float bound[G];  // rebased multi-wavefront strips: each wavefront's last base
     __shared__ unsigned slot;
@@ -490,36 +584,54 @@ __global__ __launch_bounds__(64 * G) void k_strip(const float *__restrict__ ws, 
         // unwindowed plain FP32 strips take two columns per step; the
         // compensated and FP64 cells already hold enough independent work
         // per cell (measured slower in the two-column form)
-        if constexpr (!BANDED && (std::is_same<ACC, AccPlain>::value || kRebased<ACC>))
-            strip2_item<ACC, H, G>(items[idx], ws, ser, dsi, ring, bound);
-        else
-            strip_item<ACC, H, G, BANDED>(items[idx], ws, ser, dsi, ring, bound);
+        typename ACC::T *pbuf =
+            PASSES ? static_cast<typename ACC::T *>(pass_buf) + (int64_t)blockIdx.x * pass_stride : nullptr;
+        if constexpr (!BANDED && (std::is_same<ACC, AccPlain>::value || kRebased<ACC>)) {
+            if (!PASSES || ser[dsi[items[idx].ds].series_base + items[idx].rows].len <= 64 * H * G)
+                strip2_item<ACC, H, G>(items[idx], ws, ser, dsi, ring, bound);
+            else  // several row passes: the one-column sweep
+                strip_item<ACC, H, G, BANDED, PASSES>(items[idx], ws, ser, dsi, ring, bound, pbuf);
+        } else {
+            strip_item<ACC, H, G, BANDED, PASSES>(items[idx], ws, ser, dsi, ring, bound, pbuf);
+        }
         if (!queue) break;
     }
 }
 
 template <class ACC, int H, int G>
 hipError_t strip_launch(bool banded, const float *ws, const SeriesInfo *ser, const DatasetInfo *dsi,
-                        const WaveItem *items, unsigned n, unsigned *queue, unsigned grid, hipStream_t st) {
+                        const WaveItem *items, unsigned n, unsigned *queue, unsigned grid, void *pass_buf,
+                        int64_t pass_stride, hipStream_t st) {
     const dim3 g(grid), block(64 * G);
-    if (banded)
-        hipLaunchKernelGGL((k_strip<ACC, H, G, true>), g, block, 0, st, ws, ser, dsi, items, queue, n);
+    if (banded && pass_buf)
+        hipLaunchKernelGGL((k_strip<ACC, H, G, true, true>), g, block, 0, st, ws, ser, dsi, items, queue, n,
+                           pass_buf, pass_stride);
+    else if (banded)
+        hipLaunchKernelGGL((k_strip<ACC, H, G, true, false>), g, block, 0, st, ws, ser, dsi, items, queue, n,
+                           nullptr, 0);
+    else if (pass_buf)
+        hipLaunchKernelGGL((k_strip<ACC, H, G, false, true>), g, block, 0, st, ws, ser, dsi, items, queue, n,
+                           pass_buf, pass_stride);
     else
-        hipLaunchKernelGGL((k_strip<ACC, H, G, false>), g, block, 0, st, ws, ser, dsi, items, queue, n);
+        hipLaunchKernelGGL((k_strip<ACC, H, G, false, false>), g, block, 0, st, ws, ser, dsi, items, queue, n,
+                           nullptr, 0);
     return hipGetLastError();
 }
 
 template <class ACC, int H, int G>
-int strip_slots(bool banded) {
-    return banded ? resident_blocks(reinterpret_cast<const void *>(&k_strip<ACC, H, G, true>), 64 * G)
-                  : resident_blocks(reinterpret_cast<const void *>(&k_strip<ACC, H, G, false>), 64 * G);
+int strip_slots(bool banded, bool passes) {
+    const void *k = banded ? (passes ? reinterpret_cast<const void *>(&k_strip<ACC, H, G, true, true>)
+                                     : reinterpret_cast<const void *>(&k_strip<ACC, H, G, true, false>))
+                           : (passes ? reinterpret_cast<const void *>(&k_strip<ACC, H, G, false, true>)
+                                     : reinterpret_cast<const void *>(&k_strip<ACC, H, G, false, false>));
+    return resident_blocks(k, 64 * G);
 }
 
 }  // namespace
 
 using StripFn = hipError_t (*)(bool, const float *, const SeriesInfo *, const DatasetInfo *, const WaveItem *,
-                               unsigned, unsigned *, unsigned, hipStream_t);
-using StripSlotsFn = int (*)(bool);
+                               unsigned, unsigned *, unsigned, void *, int64_t, hipStream_t);
+using StripSlotsFn = int (*)(bool, bool);
 struct StripEntry {  // one instantiated strip shape of an accumulation mode (AccMode)
     int accum, H, G;
     StripFn fn;

@@ -67,18 +67,21 @@ int strip_shapes(int accum, StripShape *out, int max_out) {
     return k;
 }
 
-int strip_resident(int accum, StripShape shape, bool banded) {
+int strip_resident(int accum, StripShape shape, bool banded, bool passes) {
     const StripEntry *e = find_strip(accum, shape);
-    return e ? e->slots(banded) : 0;
+    return e ? e->slots(banded, passes) : 0;
 }
 
 hipError_t launch_strip(int accum, StripShape shape, bool banded, const float *ws, const SeriesInfo *ser,
                         const DatasetInfo *dsi, const WaveItem *items, unsigned n_items, unsigned *queue, int slots,
-                        hipStream_t stream) {
+                        void *pass_buf, int64_t pass_stride, hipStream_t stream) {
     if (n_items == 0) return hipSuccess;
     const StripEntry *e = find_strip(accum, shape);
     if (!e) return hipErrorInvalidValue;
-    return e->fn(banded, ws, ser, dsi, items, n_items, queue, grid_for(n_items, queue, slots), stream);
+    return e->fn(banded, ws, ser, dsi, items, n_items, queue, grid_for(n_items, queue, slots), pass_buf, pass_stride,
+                 stream);
 }
+
+int strip_grid(unsigned n_items, unsigned *queue, int slots) { return (int)grid_for(n_items, queue, slots); }
 
 }  // namespace dtwmi

@@ -167,13 +167,8 @@ def test_unsupported_requests_rejected_on_host():
     # lane-band kernel with Kahan or FP64 accumulation
     assert _call_ex([4, 4], [0, 4], kernel=1, accum=B.ACCUM["kahan"])[0] == B.DTW_ERR_UNSUPPORTED
     assert _call_ex([4, 4], [0, 4], kernel=1, accum=B.ACCUM["fp64"])[0] == B.DTW_ERR_UNSUPPORTED
-    # both series of a pair longer than the wavefront kernels cover
-    rc, msg = _call_ex([40000, 40000], [0, 40000])
-    assert rc == B.DTW_ERR_UNSUPPORTED and "32768" in msg
-    rc, msg = _call_ex([20000, 20000], [0, 20000], accum=B.ACCUM["kahan"])
-    assert rc == B.DTW_ERR_UNSUPPORTED and "16384" in msg
-    rc, msg = _call_ex([40000, 40000], [0, 40000], accum=B.ACCUM["rebased"])
-    assert rc == B.DTW_ERR_UNSUPPORTED and "32768" in msg
+    # (pairs longer than one workgroup's rows are swept in row passes: no
+    # length limit to reject here; the GPU tests cover them)
 
 
 def test_accumulation_enum_matches_header():

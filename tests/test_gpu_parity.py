@@ -446,6 +446,105 @@ def test_wave_kernel_forced_rows_per_lane(H):
                           run(ds, kernel="wave", accum="plain"))
 
 
+# ---------------------------------------------------------------- row passes
+
+def _describe_plan(ds, **kw):
+    plan, series, outs = _plan_for([ds], **kw)
+    plan.execute()
+    torch.cuda.synchronize()
+    desc = plan.describe()
+    got = outs[0].cpu().numpy()[:ds.n_pairs]
+    plan.destroy()
+    return got, desc
+
+
+# (accumulation, forced rows per lane, rows of the largest shape of that height)
+ROW_PASS_CASES = [("plain", 1, 64), ("rebased", 1, 64), ("kahan", 1, 64), ("fp64", 1, 64), ("plain", 3, 192),
+                  ("kahan", 8, 512), ("fp64", 4, 256), ("plain", 16, 2048), ("rebased", 16, 2048)]
+
+
+@pytest.mark.parametrize("accum,H,cap", ROW_PASS_CASES)
+def test_row_passes_forced_small_shapes(accum, H, cap):
+    # A forced strip height whose largest shape holds fewer rows than the
+    # shorter series: the pair is swept in passes of `cap` rows, the last row
+    # of each pass handed to the next through global memory (one wavefront per
+    # pair for H <= 8; two for 16 x 2, with the LDS ring inside each pass).
+    # Shorter series of cap-1, cap, cap+1 (a one-row last pass), 2*cap, 2*cap+3
+    # and ~4.6*cap points, with and without a window.
+    _gpu()
+    rng = np.random.default_rng(4100 + H)
+    lens = [cap - 1, cap, cap + 1, 2 * cap, 2 * cap + 3, int(4.6 * cap), 1, 5]
+    series = [synth.random_walk(rng, L) for L in lens]
+    for window in (-1, max(3, cap // 5)):
+        ds = synth.pack(series, "passes", window)
+        pi, pj = oracle.all_pairs_list(ds.N)
+        ref = oracle_pairs(ds, pi, pj)
+        got, desc = _describe_plan(ds, kernel="wave", rows_per_lane=H, accum=accum)
+        what = "passes %s H=%d w=%d" % (accum, H, window)
+        print(what, flush=True)
+        if accum == "fp64":
+            assert np.array_equal(got, ref.astype(np.float32)), what
+        elif accum == "plain":
+            assert_close(got, ref, tol=plain_tol(ds), what=what)
+        else:
+            assert_close(got, ref, what=what)
+        if accum in ("plain", "kahan"):
+            # every cell is evaluated with the same operations whatever the
+            # sweep: the single-pass strips give the same bits
+            whole, _ = _run_plan(ds, kernel="wave", accum=accum)
+            assert np.array_equal(got, whole), what + ": differs from the single-pass strips"
+        # the longest shorter series is 2*cap+3 points (paired with ~4.6*cap): three passes
+        assert max(g["max_row_passes"] for g in desc["wave_groups"]) == 3
+
+
+def test_row_passes_beyond_the_largest_shapes():
+    # shorter series beyond the largest shapes, 16,384 rows for Kahan and FP64
+    # (16 x 16) and 32,768 for plain and rebased sums (64 x 8): two or three
+    # passes of a workgroup of 8 or 16 wavefronts
+    _gpu()
+    rng = np.random.default_rng(4242)
+    series = [synth.random_walk(rng, L) for L in (16385, 17000, 33000, 33100)]
+    ds = synth.pack(series, "beyond", -1)
+    pi, pj = oracle.all_pairs_list(ds.N)
+    ref = oracle_pairs(ds, pi, pj)
+    long_pairs = (np.minimum(ds.lengths[pi], ds.lengths[pj]) > 32768)
+    for accum in ("auto", "fp64", "kahan", "rebased", "plain"):
+        got = run(ds, accum=accum)
+        what = "beyond %s" % accum
+        print(what, flush=True)
+        if accum in ("auto", "fp64"):
+            # the default runs these unwindowed paths of 32,000+ cells in FP64
+            assert np.array_equal(got, ref.astype(np.float32)), what
+        elif accum == "plain":
+            assert_close(got, ref, tol=REL_TOL_LONG_PLAIN, what=what)
+        else:
+            assert_close(got, ref, what=what)
+        if accum == "plain":
+            assert long_pairs.sum() == 1
+    # a window: the default sends these pairs to rebased banded strips
+    dsw = synth.pack(series, "beyond-w", 1500)
+    refw = oracle_pairs(dsw, pi, pj)
+    assert_close(run(dsw), refw, what="beyond w=1500")
+    assert np.array_equal(run(dsw, accum="fp64"), refw.astype(np.float32)), "beyond w=1500 fp64"
+
+
+def test_rebased_window_below_finished_wavefronts():
+    # a narrow window on series of ~20,000 points: the window leaves the rows
+    # of the upper wavefronts of a workgroup long before the lower ones finish;
+    # their posted lower bound must then stop holding the lower wavefronts'
+    # bases down (else those round like plain sums, ~5e-5 at these lengths)
+    _gpu()
+    rng = np.random.default_rng(777)
+    series = [synth.random_walk(rng, L) for L in (20000, 20100, 20250, 20500)]
+    ds = synth.pack(series, "floor", 300)
+    pi, pj = oracle.all_pairs_list(ds.N)
+    ref = oracle_pairs(ds, pi, pj)
+    got, desc = _describe_plan(ds, kernel="wave", accum="rebased")
+    assert all(g["kernel"].endswith("x8") for g in desc["wave_groups"]), desc
+    assert_close(got, ref, what="rebased w=300 over 8 wavefronts")
+    assert_close(run(ds), ref, what="default w=300")
+
+
 # ---------------------------------------------------------------- pair lists
 
 def _random_pairs(rng, N, P):
