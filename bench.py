@@ -86,6 +86,12 @@ def make_datasets(name, dtype="f32"):
              "c5": synth.config5}[name]()]
 
 
+def lane_name(g):
+    """Kernel label of a lane-band group of a plan's describe JSON."""
+    ppw = g.get("pairs_per_wave", 64)
+    return "lane:%d/%s" % (g["W"], g["accum"]) + ("" if ppw == 64 else "/%d-per-wave" % ppw)
+
+
 def sources_sha256(paths):
     """SHA-256 over the bytes of the given repository files, in order."""
     import hashlib
@@ -276,7 +282,7 @@ def extra_workloads(dev, stream, steps):
         res = {"gcups": round(cells / (ms * 1e-3) / 1e9, 1), "ms_per_step": round(ms, 4),
                "kernel_ms": round(statistics.mean(kms), 4), "band_cells": cells,
                "kernels": sorted({"%s/%s" % (g_["kernel"], g_["accum"]) for g_ in desc["wave_groups"]} |
-                                 {"lane:%d/%s" % (g_["W"], g_["accum"]) for g_ in desc["lane_groups"]})}
+                                 {lane_name(g_) for g_ in desc["lane_groups"]})}
         return res, [o.cpu().numpy() for o in outs]
 
     c2, _ = rate([synth.config2()], False, max(50, steps // 2))
@@ -315,6 +321,8 @@ def main(argv=None):
     ap.add_argument("--accum", default="auto", choices=["auto", "plain", "rebased", "kahan", "fp64"])
     ap.add_argument("--rows-per-lane", type=int, default=0,
                     help="force the strip / cyclic rows per lane (0 = cost model)")
+    ap.add_argument("--pairs-per-wave", type=int, default=0, choices=[0, 2, 4, 8, 16, 64],
+                    help="force the lane-band kernel's pairs per wavefront (0 = automatic)")
     ap.add_argument("--silhouette", type=int, default=0, metavar="K",
                     help="also time dtw_silhouette on the computed matrix with K seeded random clusters")
     ap.add_argument("--path", action="store_true",
@@ -366,12 +374,13 @@ def main(argv=None):
     if pair_list is not None:
         plan = binding.PairPlan(series[0], dsets[0].lengths, dsets[0].offsets, dsets[0].window, pair_list, outs[0],
                                 dtype=dsets[0].dtype, accum=args.accum, kernel=args.kernel, timing=True,
-                                queue=args.dispatch == "queue", autotune=args.autotune)
+                                queue=args.dispatch == "queue", autotune=args.autotune,
+                                pairs_per_wave=args.pairs_per_wave)
     else:
         plan = binding.Plan([(s_, ds.lengths, ds.offsets, ds.window, o) for s_, ds, o in zip(series, dsets, outs)],
                             dtype=dsets[0].dtype, accum=args.accum, kernel=args.kernel, timing=True,
                             queue=args.dispatch == "queue", autotune=args.autotune,
-                            rows_per_lane=args.rows_per_lane)
+                            rows_per_lane=args.rows_per_lane, pairs_per_wave=args.pairs_per_wave)
     plan_s = time.perf_counter() - t_plan
     info = plan.info()
     plan_desc = plan.describe()
@@ -424,8 +433,9 @@ def main(argv=None):
                    "kernel": args.kernel, "accum": args.accum, "accum_groups": sorted(accs),
                    "storage": dsets[0].dtype,
                    "dispatch": args.dispatch, "autotune": args.autotune, "rows_per_lane": args.rows_per_lane,
+                   "pairs_per_wave": args.pairs_per_wave,
                    "kernels": ["%s/%s" % (g["kernel"], g["accum"]) for g in plan_desc["wave_groups"]] +
-                              ["lane:%d/%s" % (g["W"], g["accum"]) for g in plan_desc["lane_groups"]],
+                              [lane_name(g) for g in plan_desc["lane_groups"]],
                    "plan_create_s": round(plan_s, 3), "tuned_buckets": info["n_tuned_buckets"],
                    "tuned_changed": info["n_tuned_changed"]},
         "pct_peak_cell_rate": round(100.0 * value / (PEAK_LANE_OPS_T * 1e3 / OPS_PER_CELL), 2),

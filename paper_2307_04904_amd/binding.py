@@ -42,7 +42,8 @@ class dtw_dataset(ctypes.Structure):
 
 class dtw_options(ctypes.Structure):
     _fields_ = [("dtype", ctypes.c_int32), ("accum", ctypes.c_int32), ("kernel", ctypes.c_int32),
-                ("flags", ctypes.c_int32), ("rows_per_lane", ctypes.c_int32), ("stream", ctypes.c_void_p),
+                ("flags", ctypes.c_int32), ("rows_per_lane", ctypes.c_int32), ("pairs_per_wave", ctypes.c_int32),
+                ("stream", ctypes.c_void_p),
                 ("k_begin", ctypes.c_int64), ("k_end", ctypes.c_int64)]
 
 
@@ -137,13 +138,15 @@ def _make_dataset(series, lengths, offsets, window, out):
     return d, (ln, off)
 
 
-def _options(dtype="f32", accum="auto", kernel="auto", flags=0, stream=None, rows_per_lane=0, k_range=(0, 0)):
+def _options(dtype="f32", accum="auto", kernel="auto", flags=0, stream=None, rows_per_lane=0, k_range=(0, 0),
+             pairs_per_wave=0):
     o = dtw_options()
     o.dtype = DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
     o.accum = ACCUM[accum] if isinstance(accum, str) else int(accum)
     o.kernel = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
     o.flags = int(flags)
     o.rows_per_lane = int(rows_per_lane)
+    o.pairs_per_wave = int(pairs_per_wave)
     o.stream = _stream_handle(stream) if stream is not False else ctypes.c_void_p(0)
     o.k_begin, o.k_end = int(k_range[0]), int(k_range[1])
     return o
@@ -167,13 +170,14 @@ def dtw_pairwise_noalloc(series, lengths, offsets, window, out_condensed, dtype=
 
 
 def dtw_pairwise_ex(series, lengths, offsets, window, out_condensed, dtype="f32", accum="auto", kernel="auto",
-                    stream=None, rows_per_lane=0, queue=True, k_range=(0, 0)):
+                    stream=None, rows_per_lane=0, queue=True, k_range=(0, 0), pairs_per_wave=0):
     """One dataset with options, enqueued on `stream` (None = torch's current stream).
 
     `series` holds f32, bf16 (as int16/uint16 bits) or f16 values; k_range = (k_begin, k_end) restricts the
     written condensed entries (0, 0 = all)."""
     d, keep = _make_dataset(series, lengths, offsets, window, out_condensed)
-    o = _options(dtype, accum, kernel, 0 if queue else DTW_FLAG_NO_QUEUE, stream, rows_per_lane, k_range)
+    o = _options(dtype, accum, kernel, 0 if queue else DTW_FLAG_NO_QUEUE, stream, rows_per_lane, k_range,
+                 pairs_per_wave)
     _check(load().dtw_pairwise_ex(ctypes.byref(d), ctypes.byref(o)))
     del keep
 
@@ -186,7 +190,7 @@ class Plan:
     """
 
     def __init__(self, datasets, dtype="f32", accum="auto", kernel="auto", timing=False, rows_per_lane=0,
-                 queue=True, autotune=False, k_range=(0, 0)):
+                 queue=True, autotune=False, k_range=(0, 0), pairs_per_wave=0):
         self._lib = load()
         arr = (dtw_dataset * max(1, len(datasets)))()
         self._keep = []
@@ -196,7 +200,7 @@ class Plan:
             self._keep.append((keep, series, out))
         flags = ((DTW_FLAG_TIMING if timing else 0) | (0 if queue else DTW_FLAG_NO_QUEUE)
                  | (DTW_FLAG_AUTOTUNE if autotune else 0))
-        o = _options(dtype, accum, kernel, flags, False, rows_per_lane, k_range)
+        o = _options(dtype, accum, kernel, flags, False, rows_per_lane, k_range, pairs_per_wave)
         self._h = ctypes.c_void_p()
         _check(self._lib.dtw_plan_create(ctypes.byref(self._h), arr, len(datasets), ctypes.byref(o)))
 
@@ -241,11 +245,11 @@ def _pair_array(pairs):
 
 
 def dtw_pairs(series, lengths, offsets, window, pairs, out, dtype="f32", accum="auto", kernel="auto",
-              stream=None, queue=True, k_range=(0, 0)):
+              stream=None, queue=True, k_range=(0, 0), pairs_per_wave=0):
     """Pair-list evaluation enqueued on `stream`: out[k] = DTW(series pairs[k][0], series pairs[k][1])."""
     d, keep = _make_dataset(series, lengths, offsets, window, None)
     arr, ptr = _pair_array(pairs)
-    o = _options(dtype, accum, kernel, 0 if queue else DTW_FLAG_NO_QUEUE, stream, 0, k_range)
+    o = _options(dtype, accum, kernel, 0 if queue else DTW_FLAG_NO_QUEUE, stream, 0, k_range, pairs_per_wave)
     _check(load().dtw_pairs(ctypes.byref(d), ptr, ctypes.c_int64(len(arr)),
                             ctypes.c_void_p(out.data_ptr() if out is not None else 0), ctypes.byref(o)))
     del keep
@@ -255,14 +259,14 @@ class PairPlan(Plan):
     """dtw_plan_create_pairs: a plan over an explicit pair list of one dataset."""
 
     def __init__(self, series, lengths, offsets, window, pairs, out, dtype="f32", accum="auto", kernel="auto",
-                 timing=False, queue=True, autotune=False):
+                 timing=False, queue=True, autotune=False, pairs_per_wave=0):
         self._lib = load()
         d, keep = _make_dataset(series, lengths, offsets, window, None)
         arr, ptr = _pair_array(pairs)
         self._keep = [(keep, series, out, arr)]
         flags = ((DTW_FLAG_TIMING if timing else 0) | (0 if queue else DTW_FLAG_NO_QUEUE)
                  | (DTW_FLAG_AUTOTUNE if autotune else 0))
-        o = _options(dtype, accum, kernel, flags, False)
+        o = _options(dtype, accum, kernel, flags, False, pairs_per_wave=pairs_per_wave)
         self._h = ctypes.c_void_p()
         _check(self._lib.dtw_plan_create_pairs(ctypes.byref(self._h), ctypes.byref(d), ptr, ctypes.c_int64(len(arr)),
                                                ctypes.c_void_p(out.data_ptr()), ctypes.byref(o)))
@@ -330,21 +334,23 @@ def device_series(ds, device="cuda"):
     return t.to(device)
 
 
-def pairs_of(ds, pairs, accum="auto", kernel="auto", device="cuda"):
+def pairs_of(ds, pairs, accum="auto", kernel="auto", device="cuda", pairs_per_wave=0):
     """DTW of listed pairs of a synth.Dataset on the GPU, as a torch tensor (enqueued on the current stream)."""
     import torch
     series = device_series(ds, device)
     out = torch.full((max(1, len(pairs)),), float("nan"), dtype=torch.float32, device=device)
-    dtw_pairs(series, ds.lengths, ds.offsets, ds.window, pairs, out, dtype=ds.dtype, accum=accum, kernel=kernel)
+    dtw_pairs(series, ds.lengths, ds.offsets, ds.window, pairs, out, dtype=ds.dtype, accum=accum, kernel=kernel,
+              pairs_per_wave=pairs_per_wave)
     return out[:len(pairs)]
 
 
-def pairwise(ds, accum="auto", kernel="auto", device="cuda", out=None, rows_per_lane=0, queue=True, k_range=(0, 0)):
+def pairwise(ds, accum="auto", kernel="auto", device="cuda", out=None, rows_per_lane=0, queue=True, k_range=(0, 0),
+             pairs_per_wave=0):
     """Condensed DTW matrix of a synth.Dataset on the GPU, as a torch tensor (enqueued on the current stream)."""
     import torch
     series = device_series(ds, device)
     if out is None:
         out = torch.full((max(0, ds.n_pairs),), float("nan"), dtype=torch.float32, device=device)
     dtw_pairwise_ex(series, ds.lengths, ds.offsets, ds.window, out, dtype=ds.dtype, accum=accum, kernel=kernel,
-                    rows_per_lane=rows_per_lane, queue=queue, k_range=k_range)
+                    rows_per_lane=rows_per_lane, queue=queue, k_range=k_range, pairs_per_wave=pairs_per_wave)
     return out

@@ -13,7 +13,7 @@ PKG = os.path.dirname(HERE)
 ROOT = os.path.dirname(PKG)
 OUT_DIR = os.path.join(PKG, "_build")
 LIB = os.path.join(OUT_DIR, "libdtwmi.so")
-SOURCES = ["dtw_stage.hip", "dtw_lane.hip", "dtw_lane_rb.hip", "dtw_strip.hip", "dtw_strip_f64.hip", "dtw_cyclic.hip", "dtw_cluster.hip", "dtw_path.hip", "dtw_api.hip"]
+SOURCES = ["dtw_stage.hip", "dtw_lane.hip", "dtw_lane_rb.hip", "dtw_lane_split.hip", "dtw_strip.hip", "dtw_strip_f64.hip", "dtw_cyclic.hip", "dtw_cluster.hip", "dtw_path.hip", "dtw_api.hip"]
 ARCH = os.environ.get("DTWMI_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

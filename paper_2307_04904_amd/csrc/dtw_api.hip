@@ -29,6 +29,7 @@
 #include "dtwmi.h"
 
 #include <algorithm>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -164,7 +165,38 @@ struct LaneGroup {
     int W;
     bool rebased;
     int64_t begin, count;
+    int P = 1;  // lanes per pair: 1 (64 pairs per wavefront) or 4, 8, 16 (the split kernel)
 };
+
+// Lanes per pair of a lane-band group of 64-pair items over series of up to
+// L points: one (64 pairs per wavefront) when the items give every SIMD at
+// least two wavefronts; else the split (P = 4, 8, 16 or 32 lanes per pair,
+// items of 64/P pairs) of the smallest estimated time.  The estimate: L + P - 1
+// steps, each the longer of the dependent chain through a lane (two
+// operations per cell of its w = ceil(W/P) and five for the hand-overs, ~10
+// cycles each) and the issue of the 3w + 6 instructions of every wavefront
+// sharing its SIMD (~3.3 cycles each), all wavefronts resident at once --
+// constants fitted to the 10,000 pairs of 512 points, band 103, where 8,
+// 16 and 32 lanes per pair measured 0.078, 0.069 and 0.087 ms (4 lanes would
+// hold 26 cells, past the instances).
+int lane_split_choice(int W, bool rebased, int L, const std::vector<LaneItem> &items, int simds) {
+    if (rebased || (int64_t)items.size() >= 2LL * simds) return 1;
+    int best = 1;
+    double best_t = 0.0;
+    for (int P : {4, 8, 16, 32}) {
+        if (!lane_split_supported(P, W)) continue;
+        int64_t waves = 0;
+        for (const LaneItem &it : items) waves += (it.cnt + 64 / P - 1) / (64 / P);
+        const int w = (W + P - 1) / P;
+        const double per_simd = std::ceil((double)waves / simds);
+        const double t = (double)(L + P - 1) * std::max(10.0 * (2 * w + 5), 3.3 * (3 * w + 6) * per_simd);
+        if (best == 1 || t < best_t) {
+            best = P;
+            best_t = t;
+        }
+    }
+    return best;
+}
 
 struct WaveGroup {
     StripShape shape;  // G == 0: cyclic kernel with H = shape.H
@@ -406,6 +438,9 @@ int validate_options(const dtw_options *opt) {
         return fail(DTW_ERR_INVALID_ARG, "unknown kernel family %d", opt->kernel);
     if (opt->rows_per_lane < 0 || opt->rows_per_lane > 64)
         return fail(DTW_ERR_INVALID_ARG, "rows_per_lane=%d outside 0..64", opt->rows_per_lane);
+    if (opt->pairs_per_wave != 0 && opt->pairs_per_wave != 2 && opt->pairs_per_wave != 4 &&
+        opt->pairs_per_wave != 8 && opt->pairs_per_wave != 16 && opt->pairs_per_wave != 64)
+        return fail(DTW_ERR_INVALID_ARG, "pairs_per_wave=%d is not 0, 2, 4, 8, 16 or 64", opt->pairs_per_wave);
     if ((opt->kernel == DTW_KERNEL_CYCLIC || opt->kernel == DTW_KERNEL_LANE) &&
         (opt->accum == DTW_ACC_KAHAN || opt->accum == DTW_ACC_FP64))
         return fail(DTW_ERR_UNSUPPORTED, "the %s kernel needs AUTO, PLAIN or REBASED accumulation",
@@ -633,6 +668,7 @@ int plan_build(dtw_plan *plan_out, const dtw_dataset *ds, int32_t n_datasets, co
     const int kernel = opt ? opt->kernel : DTW_KERNEL_AUTO;
     const int flags = opt ? opt->flags : 0;
     const int force_h = opt ? opt->rows_per_lane : 0;
+    const int force_ppw = opt ? opt->pairs_per_wave : 0;
     const int64_t k_begin = opt ? opt->k_begin : 0;
     const int64_t k_end_opt = opt ? opt->k_end : 0;
 
@@ -795,10 +831,49 @@ int plan_build(dtw_plan *plan_out, const dtw_dataset *ds, int32_t n_datasets, co
     p->kernel = kernel;
     p->flags = flags;
     p->nseries = static_cast<int32_t>(ser.size());
+    // Pairs per wavefront of each lane-band group (the SIMD count from the
+    // device; 1,024 when it cannot be queried)
+    int simds = 1024;
+    if (!lane_by_w.empty()) {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+            simds = 4 * cus;
+        else
+            (void)hipGetLastError();
+    }
     for (auto &kv : lane_by_w) {
-        p->lane_groups.push_back(
-            LaneGroup{kv.first.first, kv.first.second, (int64_t)lane_items.size(), (int64_t)kv.second.size()});
-        lane_items.insert(lane_items.end(), kv.second.begin(), kv.second.end());
+        const int W = kv.first.first;
+        const bool rebased = kv.first.second;
+        int Lmax = 1;
+        for (const LaneItem &it : kv.second) Lmax = std::max(Lmax, dsi[it.ds].L);
+        int P = force_ppw ? 64 / force_ppw : lane_split_choice(W, rebased, Lmax, kv.second, simds);
+        if (P > 1 && (rebased || !lane_split_supported(P, W))) {
+            delete p;
+            return fail(DTW_ERR_UNSUPPORTED,
+                        "pairs_per_wave=%d: no split lane-band kernel for band width %d with %s sums (it needs "
+                        "PLAIN sums and 3 to %d band cells per lane)",
+                        force_ppw, W, rebased ? "rebased" : "plain", P == 32 ? 4 : (P == 16 ? 8 : 16));
+        }
+        LaneGroup g{W, rebased, (int64_t)lane_items.size(), 0, P};
+        for (const LaneItem &it : kv.second) {
+            if (P == 1) {
+                lane_items.push_back(it);
+                continue;
+            }
+            const int per = 64 / P;  // pairs per split item: partners q*per .. q*per+per-1 of the tile
+            for (int q = 0; q * per < it.cnt; ++q) {
+                LaneItem sub = it;
+                sub.cnt = std::min(per, it.cnt - q * per);
+                if (it.list < 0)
+                    sub.d0 += q * per;
+                else
+                    sub.list += q * per;
+                lane_items.push_back(sub);
+            }
+        }
+        g.count = (int64_t)lane_items.size() - g.begin;
+        p->lane_groups.push_back(g);
     }
     st.n_lane_items = static_cast<int32_t>(lane_items.size());
     st.n_wave_items = static_cast<int64_t>(wpairs.size());
@@ -1018,7 +1093,7 @@ int validate_pairs(const dtw_dataset *ds, const dtw_pair *pairs, int64_t n_pairs
 struct CacheKey {
     int device = 0;
     void *stream = nullptr;
-    int32_t dtype = 0, accum = 0, kernel = 0, flags = 0, rows = 0;
+    int32_t dtype = 0, accum = 0, kernel = 0, flags = 0, rows = 0, ppw = 0;
     int64_t k_begin = 0, k_end = 0;
     int32_t N = 0, window = 0;
     bool list = false;
@@ -1028,7 +1103,7 @@ struct CacheKey {
 
     bool operator==(const CacheKey &o) const {
         return device == o.device && stream == o.stream && dtype == o.dtype && accum == o.accum &&
-               kernel == o.kernel && flags == o.flags && rows == o.rows && k_begin == o.k_begin &&
+               kernel == o.kernel && flags == o.flags && rows == o.rows && ppw == o.ppw && k_begin == o.k_begin &&
                k_end == o.k_end && N == o.N && window == o.window && list == o.list && lengths == o.lengths &&
                offsets == o.offsets && pairs == o.pairs;
     }
@@ -1072,6 +1147,7 @@ int cached_run(const dtw_dataset &d, const dtw_options *opt, const PairRequest *
     key.kernel = o.kernel;
     key.flags = o.flags;
     key.rows = o.rows_per_lane;
+    key.ppw = o.pairs_per_wave;
     key.k_begin = o.k_begin;
     key.k_end = o.k_end;
     key.N = d.N;
@@ -1347,8 +1423,10 @@ int dtw_plan_execute(dtw_plan p, void *stream) {
         return hip_fail(e, "queue reset kernel launch");
     int q = 0;  // queue counter of the next group
     for (const LaneGroup &g : p->lane_groups) {
-        e = launch_lane(g.W, g.rebased, p->ws, p->d_ser, p->d_ds, p->d_lane + g.begin, p->d_partner,
-                        (unsigned)g.count, s);
+        e = g.P > 1 ? launch_lane_split(g.P, g.W, p->ws, p->d_ser, p->d_ds, p->d_lane + g.begin, p->d_partner,
+                                        (unsigned)g.count, s)
+                    : launch_lane(g.W, g.rebased, p->ws, p->d_ser, p->d_ds, p->d_lane + g.begin, p->d_partner,
+                                  (unsigned)g.count, s);
         if (e != hipSuccess) return hip_fail(e, "lane-band kernel launch");
     }
     // Wavefront groups: forked over the plan's streams (round robin, costliest
@@ -1412,9 +1490,9 @@ int dtw_plan_describe(dtw_plan p, char *buf, int64_t size, int64_t *needed) {
     std::string j = "{\"lane_groups\": [";
     char t[256];
     for (size_t k = 0; k < p->lane_groups.size(); ++k) {
-        snprintf(t, sizeof t, "%s{\"W\": %d, \"accum\": \"%s\", \"items\": %lld}", k ? ", " : "",
-                 p->lane_groups[k].W, p->lane_groups[k].rebased ? "rebased" : "plain",
-                 (long long)p->lane_groups[k].count);
+        snprintf(t, sizeof t, "%s{\"W\": %d, \"accum\": \"%s\", \"items\": %lld, \"pairs_per_wave\": %d}",
+                 k ? ", " : "", p->lane_groups[k].W, p->lane_groups[k].rebased ? "rebased" : "plain",
+                 (long long)p->lane_groups[k].count, 64 / p->lane_groups[k].P);
         j += t;
     }
     j += "], \"wave_groups\": [";

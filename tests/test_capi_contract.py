@@ -51,7 +51,7 @@ def test_band_cells_sweep():
 
 
 def _call_ex(lengths, offsets, N=None, window=-1, series=FAKE_DEV, out=FAKE_DEV, dtype=0, accum=0, kernel=0, flags=0,
-             k_range=(0, 0)):
+             k_range=(0, 0), pairs_per_wave=0):
     lib = B.load()
     ln = np.ascontiguousarray(lengths, dtype=np.int32)
     off = np.ascontiguousarray(offsets, dtype=np.int64)
@@ -65,6 +65,7 @@ def _call_ex(lengths, offsets, N=None, window=-1, series=FAKE_DEV, out=FAKE_DEV,
     o = B.dtw_options()
     o.dtype, o.accum, o.kernel, o.flags = dtype, accum, kernel, flags
     o.k_begin, o.k_end = k_range
+    o.pairs_per_wave = pairs_per_wave
     rc = lib.dtw_pairwise_ex(ctypes.byref(d), ctypes.byref(o))
     return rc, B.dtw_last_error()
 
@@ -188,6 +189,22 @@ def test_output_range_validated_on_host():
     # the options struct carries the range after the stream pointer
     assert B.dtw_options.k_begin.offset == 32 and B.dtw_options.k_end.offset == 40
     assert ctypes.sizeof(B.dtw_options) == 48
+
+
+def test_pairs_per_wave_validated_on_host():
+    ok_len, ok_off = [4, 4, 4], [0, 4, 8]
+    for bad in (-1, 1, 3, 32, 65):
+        rc, msg = _call_ex(ok_len, ok_off, pairs_per_wave=bad)
+        assert rc == B.DTW_ERR_INVALID_ARG and "pairs_per_wave" in msg
+    # between rows_per_lane and the stream pointer, where the struct had padding
+    assert B.dtw_options.pairs_per_wave.offset == 20 and B.dtw_options.stream.offset == 24
+    text = open(HEADER).read()
+    assert text.index("int32_t rows_per_lane;") < text.index("int32_t pairs_per_wave;") < text.index("void *stream;")
+
+
+def test_series_length_limit_on_host():
+    rc, msg = _call_ex([5, (1 << 28) + 1], [0, 5])
+    assert rc == B.DTW_ERR_UNSUPPORTED and "exceeds" in msg
 
 
 def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):

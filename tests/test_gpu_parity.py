@@ -584,9 +584,14 @@ def test_pair_list_medoids_on_lane_kernel():
         plan.execute()
         torch.cuda.synchronize()
     info = plan.info()
+    desc = plan.describe()
     plan.destroy()
     got = out.cpu().numpy()
-    assert info["n_wave_items"] == 0 and info["n_lane_items"] == len(medoids) * ((ds.N + 63) // 64)
+    # 1,500 pairs are 25 tiles of 64: the planner spreads each pair over more
+    # lanes to fill the device -- 8 (8 pairs per wavefront), the most that
+    # leaves 3 of the 25 band cells to a lane
+    assert [g["pairs_per_wave"] for g in desc["lane_groups"]] == [8]
+    assert info["n_wave_items"] == 0 and info["n_lane_items"] >= len(pairs) // 8
     full = run(ds)
     self_pair = pairs[:, 0] == pairs[:, 1]
     assert np.all(got[self_pair] == 0.0)
@@ -595,6 +600,88 @@ def test_pair_list_medoids_on_lane_kernel():
     assert np.array_equal(got[~self_pair], full[k])
     sel = np.random.default_rng(2).choice(len(pairs), 200, replace=False)
     assert_close(got[sel], oracle_pairs(ds, pairs[sel, 0], pairs[sel, 1]), what="medoid pairs")
+
+
+# ---------------------------------------------------------------- split lane-band kernel
+
+# (lanes per pair, windows): band widths 2w+1 with 3 to 4 (32 lanes), 8 (16
+# lanes) or 16 (8 and 4 lanes) cells per lane, with 1 to 31 short lanes
+SPLIT_CASES = [(32, [32, 40, 47, 48, 51, 63]), (16, [16, 20, 23, 24, 40, 51, 63]), (8, [8, 11, 12, 30, 51, 60, 63]),
+               (4, [4, 5, 13, 20, 31])]
+
+
+@pytest.mark.parametrize("P,windows", SPLIT_CASES)
+def test_split_lane_kernel_bit_identical(P, windows):
+    # every pair's band row spread over P lanes (64/P pairs per wavefront):
+    # the same cell operations as one pair per lane, so the same bits, over
+    # series just long enough for the window, shorter than one step
+    # iteration, longer than several, and tiles with fewer pairs than groups
+    _gpu()
+    ppw = 64 // P
+    checked = 0
+    for w in windows:
+        for L in sorted({w + 2, 19, 40, 131}):
+            if L < w + 2:
+                continue
+            ds = synth.small_random(seed=5000 + 7 * w + L, N=11, len_lo=L, len_hi=L, window=w)
+            split = run(ds, kernel="lane", accum="plain", pairs_per_wave=ppw)
+            whole = run(ds, kernel="lane", accum="plain", pairs_per_wave=64)
+            assert not np.any(np.isnan(split)), "P=%d w=%d L=%d: a pair was not written" % (P, w, L)
+            assert np.array_equal(split, whole), "P=%d w=%d L=%d: differs from one pair per lane" % (P, w, L)
+            if L == 131:
+                pi, pj = oracle.all_pairs_list(ds.N)
+                assert_close(split, oracle_pairs(ds, pi, pj), what="split P=%d w=%d" % (P, w))
+            checked += 1
+    assert checked >= 2 * len(windows)
+
+
+def test_split_lane_kernel_pair_lists_and_ranges():
+    from paper_2307_04904_amd import binding as B
+    _gpu()
+    ds = synth.small_random(seed=91, N=120, len_lo=200, len_hi=200, window=51)
+    rng = np.random.default_rng(3)
+    pairs = np.stack([rng.integers(0, ds.N, 700), rng.integers(0, ds.N, 700)], axis=1).astype(np.int32)
+    series = B.device_series(ds)
+    outs = {}
+    for ppw in (64, 8, 4, 2):  # band of 103 cells: 13, 7 or 4 per lane (16 pairs per wavefront would need 26)
+        out = torch.full((len(pairs),), float("nan"), device="cuda")
+        B.dtw_pairs(series, ds.lengths, ds.offsets, ds.window, pairs, out, accum="plain", pairs_per_wave=ppw)
+        torch.cuda.synchronize()
+        outs[ppw] = out.cpu().numpy()
+    for ppw in (8, 4, 2):
+        assert np.array_equal(outs[ppw], outs[64]), "pair list, %d pairs per wavefront" % ppw
+    sel = rng.choice(len(pairs), 60, replace=False)
+    assert_close(outs[4][sel], oracle_pairs(ds, pairs[sel, 0], pairs[sel, 1]), what="split pair list")
+    # a condensed sub-range: rows of the matrix in runs of 64/P partners
+    full = run(ds, accum="plain", pairs_per_wave=64)
+    k0, k1 = 1234, 4321
+    part = run(ds, accum="plain", pairs_per_wave=8, k_range=(k0, k1))
+    assert np.array_equal(part[k0:k1], full[k0:k1])
+    assert np.all(np.isnan(part[:k0])) and np.all(np.isnan(part[k1:]))
+
+
+def test_split_lane_kernel_rejections():
+    from paper_2307_04904_amd import binding as B
+    _gpu()
+    ds = synth.small_random(seed=92, N=6, len_lo=64, len_hi=64, window=3)  # band width 7
+    with pytest.raises(B.DtwError) as e:  # 16 lanes would hold fewer than 3 cells each
+        run(ds, accum="plain", pairs_per_wave=4)
+    assert e.value.code == B.DTW_ERR_UNSUPPORTED
+    long = synth.small_random(seed=93, N=4, len_lo=1500, len_hi=1500, window=20)  # rebased sums (AUTO)
+    with pytest.raises(B.DtwError) as e:
+        run(long, pairs_per_wave=8)
+    assert e.value.code == B.DTW_ERR_UNSUPPORTED
+    # automatic: the 15 pairs of 6 series fill 6 tiles, so each pair is
+    # spread over the most lanes its band allows (41 cells: 16 lanes; 32
+    # would leave fewer than 3 cells to a lane)
+    small = synth.small_random(seed=94, N=6, len_lo=64, len_hi=64, window=20)
+    plan, series, outs = _plan_for([small], accum="plain")
+    plan.execute()
+    torch.cuda.synchronize()
+    assert [g["pairs_per_wave"] for g in plan.describe()["lane_groups"]] == [4]
+    pi, pj = oracle.all_pairs_list(small.N)
+    assert_close(outs[0].cpu().numpy(), oracle_pairs(small, pi, pj), what="automatic split")
+    plan.destroy()
 
 
 # ---------------------------------------------------------------- batched plans, graph capture
