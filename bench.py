@@ -264,11 +264,13 @@ def extra_workloads(dev, stream, steps):
     from paper_2307_04904_amd import binding, synth
     out = {}
 
-    def rate(dsets, graph, n_steps, accum="auto"):
+    def rate(dsets, graph, n_steps, accum="auto", autotune=False):
         series = [binding.device_series(ds, dev) for ds in dsets]
         outs = [torch.full((max(1, ds.n_pairs),), float("nan"), device=dev) for ds in dsets]
+        t0 = time.perf_counter()
         plan = binding.Plan([(s_, ds.lengths, ds.offsets, ds.window, o) for s_, ds, o in zip(series, dsets, outs)],
-                            dtype=dsets[0].dtype, accum=accum, timing=True)
+                            dtype=dsets[0].dtype, accum=accum, timing=True, autotune=autotune)
+        plan_s = time.perf_counter() - t0
         step, g = make_step(plan, stream, graph)
         ms, _ = time_steps(step, stream, n_steps, max(3, n_steps // 10))
         cells = plan.info()["band_cells"]
@@ -283,6 +285,10 @@ def extra_workloads(dev, stream, steps):
                "kernel_ms": round(statistics.mean(kms), 4), "band_cells": cells,
                "kernels": sorted({"%s/%s" % (g_["kernel"], g_["accum"]) for g_ in desc["wave_groups"]} |
                                  {lane_name(g_) for g_ in desc["lane_groups"]})}
+        if autotune:
+            res.update(plan_create_s=round(plan_s, 2), tuned_buckets=len(desc["tuned"]),
+                       buckets_switched=sum(1 for b in desc["tuned"] if b["applied"] and b["chosen"] != b["model"]),
+                       plan_trials=desc["plan_trials"])
         return res, [o.cpu().numpy() for o in outs]
 
     c2, _ = rate([synth.config2()], False, max(50, steps // 2))
@@ -290,6 +296,10 @@ def extra_workloads(dev, stream, steps):
     c4, c4_outs = rate(synth.config4(), True, 20)
     c4["ratio_to_equal_size_rate"] = round(c4["gcups"] / c2["gcups"], 4)
     out["c4_batched_64_datasets"] = dict(c4, description=WORKLOADS["c4"], timing="hip graph replays")
+    c4t, _ = rate(synth.config4(), True, 20, autotune=True)
+    c4t["ratio_to_model_plan"] = round(c4t["gcups"] / c4["gcups"], 4)
+    out["c4_batched_autotuned"] = dict(c4t, description=WORKLOADS["c4"] + "; DTW_FLAG_AUTOTUNE (measured "
+                                       "instances, whole-plan trials)", timing="hip graph replays")
     ds3 = synth.config3()
     c3, c3_out = rate([ds3], False, 10)
     pi, pj = [], []

@@ -165,8 +165,41 @@ struct LaneGroup {
     int W;
     bool rebased;
     int64_t begin, count;
-    int P = 1;  // lanes per pair: 1 (64 pairs per wavefront) or 4, 8, 16 (the split kernel)
+    int P = 1;  // lanes per pair: 1 (64 pairs per wavefront) or 4, 8, 16, 32 (the split kernel)
+    int64_t cap = 0;  // item slots reserved for the group (autotuning: the most any split needs)
+    int model_P = 1;  // the choice before autotuning
+    std::vector<std::pair<int, float>> tuned_ms;  // autotuning: (P, ms per launch)
 };
+
+// The items of 64/P pairs of a list of 64-pair lane-band tiles (P > 1), or
+// the tiles themselves (P = 1), appended to `out`.
+void split_lane_items(const std::vector<LaneItem> &tiles, int P, std::vector<LaneItem> &out) {
+    for (const LaneItem &it : tiles) {
+        if (P == 1) {
+            out.push_back(it);
+            continue;
+        }
+        const int per = 64 / P;  // pairs per split item: partners q*per .. q*per+per-1 of the tile
+        for (int q = 0; q * per < it.cnt; ++q) {
+            LaneItem sub = it;
+            sub.cnt = std::min(per, it.cnt - q * per);
+            if (it.list < 0)
+                sub.d0 += q * per;
+            else
+                sub.list += q * per;
+            out.push_back(sub);
+        }
+    }
+}
+
+// Candidate splits of a lane-band group: 1 and every supported P (plain sums).
+std::vector<int> lane_split_candidates(int W, bool rebased) {
+    std::vector<int> c{1};
+    if (!rebased)
+        for (int P : {4, 8, 16, 32})
+            if (lane_split_supported(P, W)) c.push_back(P);
+    return c;
+}
 
 // Lanes per pair of a lane-band group of 64-pair items over series of up to
 // L points: one (64 pairs per wavefront) when the items give every SIMD at
@@ -390,8 +423,15 @@ struct TunedBucket {
     int n_ho, m_ho, b_ho;  // half-octave buckets (b_ho of b+1; -1 = no window)
     int acc;               // AccMode of the bucket's pairs
     int64_t pairs;
-    Choice model, chosen;
+    Choice model, chosen;  // chosen: the fastest measured on the bucket's own sample
     std::vector<std::pair<Choice, float>> us_per_pair;  // measured candidates
+    std::vector<int64_t> idx;  // the bucket's wavefront pairs
+    bool applied = false;      // chosen kept by the whole-plan trials
+};
+
+struct PlanTrial {  // one whole-plan timing of the autotuner
+    int switched;   // buckets given their measured choice (the rest: the model's)
+    float ms;       // execute time, median of the timed executes
 };
 
 }  // namespace
@@ -418,6 +458,9 @@ struct dtw_plan_s {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     bool timed_once = false;
     std::vector<TunedBucket> tuned;
+    std::vector<PlanTrial> trials;
+    // 64-pair tiles of each lane-band group, kept for autotuning its split
+    std::vector<std::vector<LaneItem>> lane_tiles;
     // Wavefront groups run on up to kAuxStreams streams of the plan, forked
     // from and joined back to the caller's stream, so that one group's last
     // workgroups overlap the next group's first.
@@ -614,12 +657,153 @@ int autotune(dtw_plan p, const std::vector<WavePair> &wp, std::vector<Choice> &c
         }
         if (rc != DTW_OK) break;
         for (int64_t k : idx) choice[(size_t)k] = tb.chosen;
+        tb.idx = idx;
         p->tuned.push_back(tb);
     }
     if (d_items) (void)hipFree(d_items);
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     return rc;
+}
+
+hipError_t launch_lane_group(const dtw_plan p, const LaneGroup &g, hipStream_t s) {
+    return g.P > 1 ? launch_lane_split(g.P, g.W, p->ws, p->d_ser, p->d_ds, p->d_lane + g.begin, p->d_partner,
+                                       (unsigned)g.count, s)
+                   : launch_lane(g.W, g.rebased, p->ws, p->d_ser, p->d_ds, p->d_lane + g.begin, p->d_partner,
+                                 (unsigned)g.count, s);
+}
+
+// Median of `reps` timed runs of `run` (after one untimed), in ms.
+template <class Run>
+int time_median(Run run, int reps, float *ms_out) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    std::vector<float> ms;
+    int rc = e == hipSuccess ? run() : hip_fail(e, "hipEventCreate");
+    if (rc == DTW_OK && (e = hipDeviceSynchronize()) != hipSuccess) rc = hip_fail(e, "autotune timing");
+    for (int r = 0; rc == DTW_OK && r < reps; ++r) {
+        if ((e = hipEventRecord(e0, nullptr)) != hipSuccess) {
+            rc = hip_fail(e, "hipEventRecord");
+            break;
+        }
+        if ((rc = run()) != DTW_OK) break;
+        float t = 0.0f;
+        if ((e = hipEventRecord(e1, nullptr)) != hipSuccess || (e = hipEventSynchronize(e1)) != hipSuccess ||
+            (e = hipEventElapsedTime(&t, e0, e1)) != hipSuccess) {
+            rc = hip_fail(e, "autotune timing");
+            break;
+        }
+        ms.push_back(t);
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (rc == DTW_OK) {
+        std::sort(ms.begin(), ms.end());
+        *ms_out = ms[ms.size() / 2];
+    }
+    return rc;
+}
+
+// Pairs per wavefront of every lane-band group, measured: each candidate
+// split of the group's tiles is uploaded and its launch timed on its own
+// (lane-band groups run one after the other on the caller's stream, so a
+// launch alone is what an execute sees); the fastest stays.
+int autotune_lanes(dtw_plan p) {
+    hipError_t e = launch_stage(p->d_src, p->d_ser, p->ws, p->nseries, nullptr);
+    if (e != hipSuccess) return hip_fail(e, "staging kernel launch");
+    for (size_t gi = 0; gi < p->lane_groups.size(); ++gi) {
+        LaneGroup &g = p->lane_groups[gi];
+        const std::vector<LaneItem> &tiles = p->lane_tiles[gi];
+        const std::vector<int> cands = lane_split_candidates(g.W, g.rebased);
+        if (tiles.empty() || cands.size() < 2) continue;
+        int best = g.P;
+        float best_ms = 0.0f;
+        for (int P : cands) {
+            std::vector<LaneItem> items;
+            split_lane_items(tiles, P, items);
+            if ((int64_t)items.size() > g.cap) continue;  // not reserved (cannot happen: cap is the most)
+            if ((e = hipMemcpy(p->d_lane + g.begin, items.data(), items.size() * sizeof(LaneItem),
+                               hipMemcpyHostToDevice)) != hipSuccess)
+                return hip_fail(e, "hipMemcpy (autotune)");
+            g.P = P;
+            g.count = (int64_t)items.size();
+            float ms = 0.0f;
+            const int rc = time_median(
+                [&]() {
+                    const hipError_t el = launch_lane_group(p, g, nullptr);
+                    return el == hipSuccess ? DTW_OK : hip_fail(el, "lane-band kernel launch");
+                },
+                3, &ms);
+            if (rc) return rc;
+            g.tuned_ms.push_back({P, ms});
+            if (g.tuned_ms.size() == 1 || ms < best_ms) {
+                best = P;
+                best_ms = ms;
+            }
+        }
+        std::vector<LaneItem> items;
+        split_lane_items(tiles, best, items);
+        if ((e = hipMemcpy(p->d_lane + g.begin, items.data(), items.size() * sizeof(LaneItem),
+                           hipMemcpyHostToDevice)) != hipSuccess)
+            return hip_fail(e, "hipMemcpy (autotune)");
+        g.P = best;
+        g.count = (int64_t)items.size();
+    }
+    return DTW_OK;
+}
+
+// Whole-plan trials of the measured bucket choices: each bucket's winner was
+// measured on the bucket's sample alone, at the full occupancy of one
+// instance, while an execute runs many instances side by side on several
+// streams -- so a winner alone is not always a winner in the plan.  The
+// buckets whose winner differs from the model are ranked by the measured
+// gain (time per pair saved x pairs); the plan is built and timed (median of
+// three executes) with the model's choices and with the top quarter, half,
+// three quarters and all of them switched, and the fastest of those stays.
+// The model's plan is one of the trials, so tuning never ends slower than
+// the model on the measured runs.
+template <class Assign>
+int autotune_plan(dtw_plan p, const std::vector<WavePair> &wp, const std::vector<Choice> &model, Assign &assign) {
+    std::vector<size_t> cand;
+    for (size_t b = 0; b < p->tuned.size(); ++b)
+        if (!(p->tuned[b].chosen == p->tuned[b].model)) cand.push_back(b);
+    auto gain = [&](size_t b) {
+        const TunedBucket &t = p->tuned[b];
+        double um = 0.0, uc = 0.0;
+        for (const auto &x : t.us_per_pair) {
+            if (x.first == t.model) um = x.second;
+            if (x.first == t.chosen) uc = x.second;
+        }
+        return (um - uc) * (double)t.pairs;
+    };
+    std::stable_sort(cand.begin(), cand.end(), [&](size_t a, size_t b) { return gain(a) > gain(b); });
+    std::vector<int> ks;
+    for (int q = 0; q <= 4; ++q) {
+        const int k = (int)((cand.size() * q + 3) / 4);
+        if (ks.empty() || ks.back() != k) ks.push_back(k);
+    }
+    auto choices = [&](int k) {
+        std::vector<Choice> c = model;
+        for (int i = 0; i < k; ++i)
+            for (int64_t idx : p->tuned[cand[(size_t)i]].idx) c[(size_t)idx] = p->tuned[cand[(size_t)i]].chosen;
+        return c;
+    };
+    int best_k = 0;
+    float best_ms = 0.0f;
+    for (int k : ks) {
+        int rc = assign(choices(k));
+        float ms = 0.0f;
+        if (rc == DTW_OK) rc = time_median([&]() { return dtw_plan_execute(p, nullptr); }, 3, &ms);
+        if (rc) return rc;
+        p->trials.push_back(PlanTrial{k, ms});
+        if (p->trials.size() == 1 || ms < best_ms) {
+            best_k = k;
+            best_ms = ms;
+        }
+    }
+    for (int i = 0; i < best_k; ++i) p->tuned[cand[(size_t)i]].applied = true;
+    return assign(choices(best_k));
 }
 
 std::string choice_name(Choice c) {
@@ -856,26 +1040,28 @@ int plan_build(dtw_plan *plan_out, const dtw_dataset *ds, int32_t n_datasets, co
                         force_ppw, W, rebased ? "rebased" : "plain", P == 32 ? 4 : (P == 16 ? 8 : 16));
         }
         LaneGroup g{W, rebased, (int64_t)lane_items.size(), 0, P};
-        for (const LaneItem &it : kv.second) {
-            if (P == 1) {
-                lane_items.push_back(it);
-                continue;
-            }
-            const int per = 64 / P;  // pairs per split item: partners q*per .. q*per+per-1 of the tile
-            for (int q = 0; q * per < it.cnt; ++q) {
-                LaneItem sub = it;
-                sub.cnt = std::min(per, it.cnt - q * per);
-                if (it.list < 0)
-                    sub.d0 += q * per;
-                else
-                    sub.list += q * per;
-                lane_items.push_back(sub);
-            }
-        }
+        g.model_P = P;
+        split_lane_items(kv.second, P, lane_items);
         g.count = (int64_t)lane_items.size() - g.begin;
+        g.cap = g.count;
+        if ((flags & DTW_FLAG_AUTOTUNE) && !force_ppw) {
+            // room for the split with the most items, which the tuner may try
+            int64_t most = g.count;
+            for (int c : lane_split_candidates(W, rebased)) {
+                int64_t n = 0;
+                for (const LaneItem &it : kv.second) n += c == 1 ? 1 : (it.cnt + 64 / c - 1) / (64 / c);
+                most = std::max(most, n);
+            }
+            g.cap = most;
+            lane_items.resize((size_t)(g.begin + g.cap));  // the extra slots stay unused until a trial fills them
+            p->lane_tiles.push_back(kv.second);
+        } else {
+            p->lane_tiles.emplace_back();
+        }
         p->lane_groups.push_back(g);
     }
-    st.n_lane_items = static_cast<int32_t>(lane_items.size());
+    st.n_lane_items = 0;
+    for (const LaneGroup &g : p->lane_groups) st.n_lane_items += static_cast<int32_t>(g.count);
     st.n_wave_items = static_cast<int64_t>(wpairs.size());
 
     // ---- device allocation and upload of everything but the wavefront items ----
@@ -937,89 +1123,86 @@ int plan_build(dtw_plan *plan_out, const dtw_dataset *ds, int32_t n_datasets, co
     }
 
     // ---- kernel instance of every wavefront pair: cost model, or measured ----
-    std::vector<Choice> choice(wpairs.size());
-    for (size_t k = 0; k < wpairs.size(); ++k) choice[k] = model_choice(kernel, force_h, wpairs[k]);
-    if ((flags & DTW_FLAG_AUTOTUNE) && !wpairs.empty()) {
-        rc = autotune(p, wpairs, choice, kernel, force_h);
-        if (rc) {
-            destroy_plan(p);
-            return rc;
-        }
-        st.n_tuned_buckets = static_cast<int32_t>(p->tuned.size());
-        for (const TunedBucket &t : p->tuned) st.n_tuned_changed += t.chosen == t.model ? 0 : 1;
-    }
+    std::vector<Choice> model(wpairs.size());
+    for (size_t k = 0; k < wpairs.size(); ++k) model[k] = model_choice(kernel, force_h, wpairs[k]);
+    const int64_t lane_cells = st.computed_cells;  // the lane-band tiles' share
+    const bool use_queue = !(flags & DTW_FLAG_NO_QUEUE) && !wpairs.empty();
 
-    // Group by kernel instance (H, G, banded, accumulation); inside a group
-    // costlier pairs first, groups in decreasing order of their costliest pair.
-    using Kind = std::tuple<int, int, bool, int>;  // H, G, banded, AccMode
-    std::map<Kind, std::vector<std::pair<int64_t, WaveItem>>> wave_by_kind;
-    std::map<Kind, std::pair<int64_t, int64_t>> cells_by_kind;  // admissible, swept
-    std::map<Kind, std::pair<int64_t, int64_t>> extent_by_kind;  // longest rows, cols
-    for (size_t k = 0; k < wpairs.size(); ++k) {
-        const Choice c = choice[k];
-        const WavePair &w = wpairs[k];
-        const int64_t swept = choice_steps_cells(c, w);
-        st.computed_cells += swept;
-        st.n_cyclic_items += c.cyclic() ? 1 : 0;
-        const Kind kind = std::make_tuple(c.H, c.G, c.cyclic() || w.b >= 0, (int)w.acc);
-        wave_by_kind[kind].push_back({choice_cost(c, w), make_item(c, w)});
-        auto &cells = cells_by_kind[kind];
-        cells.first += band_cells(w.n, w.m, w.b);
-        cells.second += swept;
-        auto &ext = extent_by_kind[kind];
-        ext.first = std::max<int64_t>(ext.first, c.cyclic() ? w.m : w.n);
-        ext.second = std::max<int64_t>(ext.second, c.cyclic() ? w.n : w.m);
-    }
-    std::vector<decltype(wave_by_kind)::iterator> order;
-    for (auto it = wave_by_kind.begin(); it != wave_by_kind.end(); ++it) {
-        std::stable_sort(it->second.begin(), it->second.end(),
-                         [](const std::pair<int64_t, WaveItem> &a, const std::pair<int64_t, WaveItem> &b) {
-                             return a.first > b.first;
-                         });
-        order.push_back(it);
-    }
-    std::stable_sort(order.begin(), order.end(),
-                     [](const auto &a, const auto &b) { return a->second[0].first > b->second[0].first; });
-    std::vector<WaveItem> wave_items;
-    wave_items.reserve(wpairs.size());
-    for (auto it : order) {
-        auto &v = it->second;
-        if (v.size() > 0x7fffffff) {
-            destroy_plan(p);
-            return fail(DTW_ERR_UNSUPPORTED, "more than 2^31-1 work items for one kernel");
+    // Group the wavefront pairs by kernel instance (H, G, banded, accumulation);
+    // inside a group costlier pairs first, groups in decreasing order of their
+    // costliest pair; upload the items, size the launches and the row-pass
+    // buffers.  Called again by the autotuner for each whole-plan trial.
+    auto assign = [&](const std::vector<Choice> &choice) -> int {
+        p->wave_groups.clear();
+        if (p->pass_block) {
+            (void)hipFree(p->pass_block);
+            p->pass_block = nullptr;
         }
-        const StripShape sh{std::get<0>(it->first), std::get<1>(it->first)};
-        const auto &cells = cells_by_kind[it->first];
-        const auto &ext = extent_by_kind[it->first];
-        p->wave_groups.push_back(WaveGroup{sh, std::get<2>(it->first), std::get<3>(it->first),
-                                           (int64_t)wave_items.size(), (int64_t)v.size(), 0, cells.first,
-                                           cells.second, ext.first, ext.second});
-        for (auto &e2 : v) wave_items.push_back(e2.second);
-    }
-    if (p->wave_groups.size() > (size_t)kMaxQueues) {
-        destroy_plan(p);
-        return fail(DTW_ERR_UNSUPPORTED, "more than %d wavefront kernel groups", kMaxQueues);
-    }
-    if (!wave_items.empty() &&
-        (e = hipMemcpy(p->d_wave, wave_items.data(), wave_items.size() * sizeof(WaveItem), hipMemcpyHostToDevice)) !=
-            hipSuccess) {
-        destroy_plan(p);
-        return hip_fail(e, "hipMemcpy (plan upload)");
-    }
-
-    const bool use_queue = !(flags & DTW_FLAG_NO_QUEUE) && !p->wave_groups.empty();
-    p->n_queue = use_queue ? (int)p->wave_groups.size() : 0;
-    p->d_queue = p->n_queue ? reinterpret_cast<unsigned *>(base + o_queue) : nullptr;
-    auto needs_passes = [](const WaveGroup &g) {
-        return g.shape.G > 0 && g.max_rows > (int64_t)64 * g.shape.H * g.shape.G;
-    };
-    if (use_queue)  // grid of each launch: the workgroups the device holds at once
-        for (WaveGroup &g : p->wave_groups)
-            g.slots = g.shape.G == 0 ? cyclic_resident(g.shape.H, g.acc == kAccRebased)
-                                     : strip_resident(g.acc, g.shape, g.banded, needs_passes(g));
-    // Row-pass buffers: one row of the longest swept series per workgroup of
-    // every strip group holding a pair of more than 64*H*G rows.
-    {
+        st.computed_cells = lane_cells;
+        st.n_cyclic_items = 0;
+        st.n_lane_items = 0;
+        for (const LaneGroup &g : p->lane_groups) st.n_lane_items += static_cast<int32_t>(g.count);
+        st.workspace_bytes = static_cast<int64_t>(p->dev_bytes);
+        using Kind = std::tuple<int, int, bool, int>;  // H, G, banded, AccMode
+        std::map<Kind, std::vector<std::pair<int64_t, WaveItem>>> wave_by_kind;
+        std::map<Kind, std::pair<int64_t, int64_t>> cells_by_kind;   // admissible, swept
+        std::map<Kind, std::pair<int64_t, int64_t>> extent_by_kind;  // longest rows, cols
+        for (size_t k = 0; k < wpairs.size(); ++k) {
+            const Choice c = choice[k];
+            const WavePair &w = wpairs[k];
+            const int64_t swept = choice_steps_cells(c, w);
+            st.computed_cells += swept;
+            st.n_cyclic_items += c.cyclic() ? 1 : 0;
+            const Kind kind = std::make_tuple(c.H, c.G, c.cyclic() || w.b >= 0, (int)w.acc);
+            wave_by_kind[kind].push_back({choice_cost(c, w), make_item(c, w)});
+            auto &cells = cells_by_kind[kind];
+            cells.first += band_cells(w.n, w.m, w.b);
+            cells.second += swept;
+            auto &ext = extent_by_kind[kind];
+            ext.first = std::max<int64_t>(ext.first, c.cyclic() ? w.m : w.n);
+            ext.second = std::max<int64_t>(ext.second, c.cyclic() ? w.n : w.m);
+        }
+        std::vector<typename decltype(wave_by_kind)::iterator> order;
+        for (auto it = wave_by_kind.begin(); it != wave_by_kind.end(); ++it) {
+            std::stable_sort(it->second.begin(), it->second.end(),
+                             [](const std::pair<int64_t, WaveItem> &x, const std::pair<int64_t, WaveItem> &y) {
+                                 return x.first > y.first;
+                             });
+            order.push_back(it);
+        }
+        std::stable_sort(order.begin(), order.end(),
+                         [](const auto &x, const auto &y) { return x->second[0].first > y->second[0].first; });
+        std::vector<WaveItem> wave_items;
+        wave_items.reserve(wpairs.size());
+        for (auto it : order) {
+            auto &v = it->second;
+            if (v.size() > 0x7fffffff) return fail(DTW_ERR_UNSUPPORTED, "more than 2^31-1 work items for one kernel");
+            const StripShape sh{std::get<0>(it->first), std::get<1>(it->first)};
+            const auto &cells = cells_by_kind[it->first];
+            const auto &ext = extent_by_kind[it->first];
+            p->wave_groups.push_back(WaveGroup{sh, std::get<2>(it->first), std::get<3>(it->first),
+                                               (int64_t)wave_items.size(), (int64_t)v.size(), 0, cells.first,
+                                               cells.second, ext.first, ext.second});
+            for (auto &e2 : v) wave_items.push_back(e2.second);
+        }
+        if (p->wave_groups.size() > (size_t)kMaxQueues)
+            return fail(DTW_ERR_UNSUPPORTED, "more than %d wavefront kernel groups", kMaxQueues);
+        hipError_t e2 = hipSuccess;
+        if (!wave_items.empty() &&
+            (e2 = hipMemcpy(p->d_wave, wave_items.data(), wave_items.size() * sizeof(WaveItem),
+                            hipMemcpyHostToDevice)) != hipSuccess)
+            return hip_fail(e2, "hipMemcpy (plan upload)");
+        p->n_queue = use_queue ? (int)p->wave_groups.size() : 0;
+        p->d_queue = p->n_queue ? reinterpret_cast<unsigned *>(base + o_queue) : nullptr;
+        auto needs_passes = [](const WaveGroup &g) {
+            return g.shape.G > 0 && g.max_rows > (int64_t)64 * g.shape.H * g.shape.G;
+        };
+        if (use_queue)  // grid of each launch: the workgroups the device holds at once
+            for (WaveGroup &g : p->wave_groups)
+                g.slots = g.shape.G == 0 ? cyclic_resident(g.shape.H, g.acc == kAccRebased)
+                                         : strip_resident(g.acc, g.shape, g.banded, needs_passes(g));
+        // Row-pass buffers: one row of the longest swept series per workgroup of
+        // every strip group holding a pair of more than 64*H*G rows.
         size_t pass_bytes = 0;
         std::vector<size_t> pass_off(p->wave_groups.size(), 0);
         for (size_t k = 0; k < p->wave_groups.size(); ++k) {
@@ -1030,11 +1213,9 @@ int plan_build(dtw_plan *plan_out, const dtw_dataset *ds, int32_t n_datasets, co
             pass_bytes = align_up(pass_bytes + (size_t)grid * (size_t)g.max_cols * strip_cell_bytes(g.acc), 256);
         }
         if (pass_bytes) {
-            if ((e = hipMalloc(&p->pass_block, pass_bytes)) != hipSuccess) {
-                destroy_plan(p);
+            if ((e2 = hipMalloc(&p->pass_block, pass_bytes)) != hipSuccess)
                 return fail(DTW_ERR_OUT_OF_MEMORY, "hipMalloc(%zu bytes) for row passes: %s", pass_bytes,
-                            hipGetErrorString(e));
-            }
+                            hipGetErrorString(e2));
             for (size_t k = 0; k < p->wave_groups.size(); ++k)
                 if (pass_off[k]) {
                     p->wave_groups[k].pass_buf = static_cast<char *>(p->pass_block) + (pass_off[k] - 1);
@@ -1042,10 +1223,22 @@ int plan_build(dtw_plan *plan_out, const dtw_dataset *ds, int32_t n_datasets, co
                 }
             st.workspace_bytes += (int64_t)pass_bytes;
         }
-    }
-    st.n_launches = (p->nseries > 0 ? 1 : 0) + (use_queue ? 1 : 0) +
-                    (int32_t)(p->lane_groups.size() + p->wave_groups.size());
-    p->stats = st;
+        st.n_launches = (p->nseries > 0 ? 1 : 0) + (use_queue ? 1 : 0) +
+                        (int32_t)(p->lane_groups.size() + p->wave_groups.size());
+        p->stats = st;
+        return DTW_OK;
+    };
+
+    auto plan_streams = [&](size_t groups) -> int {  // default-priority streams, events without timing
+        if (p->n_aux || groups <= 1) return DTW_OK;
+        p->n_aux = std::min<int>(kAuxStreams, (int)groups);
+        hipError_t e2 = hipEventCreateWithFlags(&p->fork_ev, hipEventDisableTiming);
+        for (int a = 0; a < p->n_aux && e2 == hipSuccess; ++a) {
+            e2 = hipStreamCreateWithFlags(&p->aux[a], hipStreamNonBlocking);
+            if (e2 == hipSuccess) e2 = hipEventCreateWithFlags(&p->join_ev[a], hipEventDisableTiming);
+        }
+        return e2 == hipSuccess ? DTW_OK : hip_fail(e2, "plan stream set-up");
+    };
 
     if (flags & DTW_FLAG_TIMING) {
         if ((e = hipEventCreate(&p->ev0)) != hipSuccess || (e = hipEventCreate(&p->ev1)) != hipSuccess) {
@@ -1053,16 +1246,27 @@ int plan_build(dtw_plan *plan_out, const dtw_dataset *ds, int32_t n_datasets, co
             return hip_fail(e, "hipEventCreate");
         }
     }
-    if (p->wave_groups.size() > 1) {  // default-priority streams, events without timing
-        p->n_aux = std::min<int>(kAuxStreams, (int)p->wave_groups.size());
-        e = hipEventCreateWithFlags(&p->fork_ev, hipEventDisableTiming);
-        for (int a = 0; a < p->n_aux && e == hipSuccess; ++a) {
-            e = hipStreamCreateWithFlags(&p->aux[a], hipStreamNonBlocking);
-            if (e == hipSuccess) e = hipEventCreateWithFlags(&p->join_ev[a], hipEventDisableTiming);
-        }
-        if (e != hipSuccess) {
+    if (flags & DTW_FLAG_AUTOTUNE) {
+        rc = autotune_lanes(p);
+        std::vector<Choice> iso = model;
+        if (rc == DTW_OK && wpairs.empty()) rc = assign(model);
+        if (rc == DTW_OK && !wpairs.empty()) rc = autotune(p, wpairs, iso, kernel, force_h);
+        if (rc == DTW_OK && !wpairs.empty()) rc = plan_streams(kAuxStreams);
+        if (rc == DTW_OK && !wpairs.empty()) rc = autotune_plan(p, wpairs, model, assign);
+        if (rc) {
             destroy_plan(p);
-            return hip_fail(e, "plan stream set-up");
+            return rc;
+        }
+        st.n_tuned_buckets = static_cast<int32_t>(p->tuned.size());
+        for (const TunedBucket &t : p->tuned) st.n_tuned_changed += t.applied && !(t.chosen == t.model) ? 1 : 0;
+        p->stats.n_tuned_buckets = st.n_tuned_buckets;
+        p->stats.n_tuned_changed = st.n_tuned_changed;
+    } else {
+        rc = assign(model);
+        if (rc == DTW_OK) rc = plan_streams(p->wave_groups.size());
+        if (rc) {
+            destroy_plan(p);
+            return rc;
         }
     }
     *plan_out = p;
@@ -1422,13 +1626,8 @@ int dtw_plan_execute(dtw_plan p, void *stream) {
     if (p->n_queue && (e = launch_zero(p->d_queue, p->n_queue, s)) != hipSuccess)
         return hip_fail(e, "queue reset kernel launch");
     int q = 0;  // queue counter of the next group
-    for (const LaneGroup &g : p->lane_groups) {
-        e = g.P > 1 ? launch_lane_split(g.P, g.W, p->ws, p->d_ser, p->d_ds, p->d_lane + g.begin, p->d_partner,
-                                        (unsigned)g.count, s)
-                    : launch_lane(g.W, g.rebased, p->ws, p->d_ser, p->d_ds, p->d_lane + g.begin, p->d_partner,
-                                  (unsigned)g.count, s);
-        if (e != hipSuccess) return hip_fail(e, "lane-band kernel launch");
-    }
+    for (const LaneGroup &g : p->lane_groups)
+        if ((e = launch_lane_group(p, g, s)) != hipSuccess) return hip_fail(e, "lane-band kernel launch");
     // Wavefront groups: forked over the plan's streams (round robin, costliest
     // group first), then joined back into `s` -- also after a failed launch,
     // so that `s` never returns (or ends a capture) with work of the plan's
@@ -1490,10 +1689,18 @@ int dtw_plan_describe(dtw_plan p, char *buf, int64_t size, int64_t *needed) {
     std::string j = "{\"lane_groups\": [";
     char t[256];
     for (size_t k = 0; k < p->lane_groups.size(); ++k) {
-        snprintf(t, sizeof t, "%s{\"W\": %d, \"accum\": \"%s\", \"items\": %lld, \"pairs_per_wave\": %d}",
-                 k ? ", " : "", p->lane_groups[k].W, p->lane_groups[k].rebased ? "rebased" : "plain",
-                 (long long)p->lane_groups[k].count, 64 / p->lane_groups[k].P);
+        const LaneGroup &g = p->lane_groups[k];
+        snprintf(t, sizeof t,
+                 "%s{\"W\": %d, \"accum\": \"%s\", \"items\": %lld, \"pairs_per_wave\": %d, "
+                 "\"model_pairs_per_wave\": %d, \"tuned_ms\": {",
+                 k ? ", " : "", g.W, g.rebased ? "rebased" : "plain", (long long)g.count, 64 / g.P, 64 / g.model_P);
         j += t;
+        for (size_t c = 0; c < g.tuned_ms.size(); ++c) {  // measured launch time per pairs-per-wavefront value
+            snprintf(t, sizeof t, "%s\"%d\": %.4g", c ? ", " : "", 64 / g.tuned_ms[c].first,
+                     (double)g.tuned_ms[c].second);
+            j += t;
+        }
+        j += "}}";
     }
     j += "], \"wave_groups\": [";
     for (size_t k = 0; k < p->wave_groups.size(); ++k) {
@@ -1514,11 +1721,11 @@ int dtw_plan_describe(dtw_plan p, char *buf, int64_t size, int64_t *needed) {
         const TunedBucket &b = p->tuned[k];
         snprintf(t, sizeof t,
                  "%s{\"n\": [%lld, %lld], \"m\": [%lld, %lld], \"band\": %s, \"accum\": \"%s\", \"pairs\": %lld, "
-                 "\"model\": \"%s\", \"chosen\": \"%s\", \"us_per_pair\": {",
+                 "\"model\": \"%s\", \"chosen\": \"%s\", \"applied\": %s, \"us_per_pair\": {",
                  k ? ", " : "", (long long)half_octave_lo(b.n_ho), (long long)half_octave_lo(b.n_ho + 1) - 1,
                  (long long)half_octave_lo(b.m_ho), (long long)half_octave_lo(b.m_ho + 1) - 1,
                  b.b_ho < 0 ? "null" : "[]", acc_name(b.acc), (long long)b.pairs, choice_name(b.model).c_str(),
-                 choice_name(b.chosen).c_str());
+                 choice_name(b.chosen).c_str(), b.applied ? "true" : "false");
         std::string entry = t;
         if (b.b_ho >= 0) {  // band range of the bucket: b + 1 in [lo, hi]
             snprintf(t, sizeof t, "[%lld, %lld]", (long long)half_octave_lo(b.b_ho) - 1,
@@ -1532,6 +1739,12 @@ int dtw_plan_describe(dtw_plan p, char *buf, int64_t size, int64_t *needed) {
             j += t;
         }
         j += "}}";
+    }
+    j += "], \"plan_trials\": [";  // whole-plan timings of the autotuner: buckets switched, ms per execute
+    for (size_t k = 0; k < p->trials.size(); ++k) {
+        snprintf(t, sizeof t, "%s{\"switched\": %d, \"ms\": %.4g}", k ? ", " : "", p->trials[k].switched,
+                 (double)p->trials[k].ms);
+        j += t;
     }
     j += "]}";
     *needed = (int64_t)j.size() + 1;

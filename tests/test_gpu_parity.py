@@ -777,6 +777,17 @@ def test_autotuned_plan_matches_cost_model_plan():
     for b in desc["tuned"]:
         assert b["chosen"] in b["us_per_pair"] and b["model"] in b["us_per_pair"]
         assert min(b["us_per_pair"].values()) == b["us_per_pair"][b["chosen"]] > 0
+    # whole-plan trials: the model's plan first, the kept one the fastest measured
+    trials = desc["plan_trials"]
+    assert trials and trials[0]["switched"] == 0 and all(t["ms"] > 0 for t in trials)
+    kept = sum(1 for b in desc["tuned"] if b["applied"])
+    assert kept in [t["switched"] for t in trials]
+    assert min(t["ms"] for t in trials) == [t["ms"] for t in trials if t["switched"] == kept][0]
+    assert info["n_tuned_changed"] == sum(1 for b in desc["tuned"] if b["applied"] and b["chosen"] != b["model"])
+    # pairs per wavefront measured for the lane-band dataset (band 11: one pair per lane or 16 lanes each)
+    lane = desc["lane_groups"][0]
+    assert sorted(lane["tuned_ms"]) == ["16", "64"] and lane["model_pairs_per_wave"] in (16, 64)
+    assert lane["tuned_ms"][str(lane["pairs_per_wave"])] == min(lane["tuned_ms"].values())
     assert sum(g["items"] for g in desc["wave_groups"]) == dsets[0].n_pairs + dsets[1].n_pairs
     for d, ds in enumerate(dsets):
         assert np.array_equal(got[True][d], got[False][d]), "dataset %d" % d
