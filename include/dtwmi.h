@@ -331,9 +331,14 @@ int dtw_assign(const float *D, int32_t N, const int32_t *centroids, int32_t K, i
  *   C (device float[n*m], may be NULL): the cumulative cost matrix, row-major,
  *     C[i*m + j] = c(i+1, j+1), +inf at inadmissible cells.
  * If c(n, m) is not finite (FP32 overflow) the path is admissible but not meaningful.
- * Allocates a device workspace of about 4 bytes per cell of the n x m matrix
- * (plus padding), runs on `stream` (hipStream_t, NULL = default) and
- * synchronises it before returning.
+ * Workspace: with C == NULL the sweep stores only each cell's move (2 bits a
+ * cell, about n*m/4 bytes plus padding) in a device buffer that the library
+ * keeps between calls, one per device, grown to the largest pair so far up
+ * to 1 GiB (larger ones are allocated for the call); calls on one device
+ * take turns on it (a lock held until the call's stream has finished).  With
+ * C the sweep keeps every cost, about 4 bytes a cell, allocated for the call.
+ * Runs on `stream` (hipStream_t, NULL = default) and synchronises it before
+ * returning.
  */
 int dtw_path(const float *x, int32_t n, const float *y, int32_t m, int32_t window, int32_t *path,
              int64_t *path_len, float *cost, float *C, void *stream);

@@ -7,15 +7,20 @@
 // workgroup of G wavefronts, lane l of wavefront g owning rows
 // [(64g+l)H, (64g+l)H+H) of the shorter series, column s - l - g(64+kLag) at
 // step s, the strip's bottom cell passed down by DPP and between wavefronts
-// through an LDS ring -- and stores every cell.  The store layout follows the
-// sweep, not the matrix: at step s wavefront g writes one contiguous block of
-// 64*H floats, lane l's H cells at Z[((s*G + g)*64 + l)*H + h], as 16-byte
-// vector stores.  k_backtrack reads that layout through zindex(); k_row_major
-// rewrites it as the row-major matrix when the caller asks for it.
+// through an LDS ring -- and stores, for every cell, either its cost or the
+// move the walk back takes from it.  The store layout follows the sweep, not
+// the matrix: at step s wavefront g writes one contiguous block per lane,
+// lane l's H values at ((s*G + g)*64 + l)*H + h (costs, 16-byte vector
+// stores) or its H 2-bit moves in ceil(H/16) words at ((s*G + g)*64 + l)*W2
+// + h/16 (moves).  When the caller asks for the cost matrix the sweep stores
+// costs, k_backtrack decides the moves from them and k_row_major rewrites
+// them row-major; otherwise it stores the moves (2 bits a cell, a sixteenth
+// of the memory) and k_backtrack_moves follows them.
 #include "dtw_device.h"
 #include "dtwmi.h"
 
 #include <cstdio>
+#include <mutex>
 
 namespace dtwmi {
 namespace {
@@ -38,6 +43,17 @@ __device__ __forceinline__ int64_t zindex(const PathGeom &g, int r, int c) {
     return ((s * g.G + wave) * 64 + lane) * g.H + h;
 }
 
+// Word and bit offset of the 2-bit move of sweep cell (r, c) (W2 words per
+// lane and step).
+__device__ __forceinline__ int64_t mindex(const PathGeom &g, int r, int c) {
+    const int L = r >> g.logH, h = r & (g.H - 1);
+    const int wave = L >> 6, lane = L & 63;
+    const int64_t s = (int64_t)c + lane + wave * (64 + kLag);
+    const int W2 = (g.H + 15) >> 4;
+    return ((s * g.G + wave) * 64 + lane) * W2 + (h >> 4);
+}
+__device__ __forceinline__ int mshift(const PathGeom &g, int r) { return 2 * (r & (g.H - 1) & 15); }
+
 // c(i+1, j+1) of Eq. (c) for 0-based (i, j) in the caller's orientation (i
 // over x, j over y), +inf for i < 0 or j < 0 (the border of the recurrence).
 __device__ __forceinline__ float cell_at(const float *__restrict__ Z, const PathGeom &g, int i, int j) {
@@ -45,9 +61,20 @@ __device__ __forceinline__ float cell_at(const float *__restrict__ Z, const Path
     return Z[g.swap ? zindex(g, j, i) : zindex(g, i, j)];
 }
 
-template <int H, int G, bool BANDED>
+// The walk's move out of a cell in the caller's orientation: 3 to (i-1, j-1),
+// 1 to (i-1, j), 2 to (i, j-1) -- the predecessor of smallest cumulative cost,
+// ties in that order.
+__device__ __forceinline__ unsigned move_code(float diag, float cu, float cl) {
+    return (diag <= cu && diag <= cl) ? 3u : (cu <= cl ? 1u : 2u);
+}
+
+// MODE 0: store costs in Z.  MODE 1, 2: store the 2-bit moves in M (1: the
+// sweep rows are the caller's i, 2: they are its j) and c(n, m) in *cost.
+template <int H, int G, bool BANDED, int MODE>
 __global__ __launch_bounds__(64 * G) void k_cost_matrix(const float *__restrict__ a, const float *__restrict__ b,
-                                                        const PathGeom geo, int band, float *__restrict__ Z) {
+                                                        const PathGeom geo, int band, float *__restrict__ Z,
+                                                        unsigned *__restrict__ M, float *__restrict__ cost) {
+    constexpr int W2 = (H + 15) / 16;  // move words per lane and step
     __shared__ float ring[G > 1 ? G - 1 : 1][kPRing];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -80,9 +107,13 @@ __global__ __launch_bounds__(64 * G) void k_cost_matrix(const float *__restrict_
     float ynext = yblock(0), yv = 0.0f;
     float up_in = kInf;
     float diag_in = (lane == 0 && wave == 0) ? 0.0f : kInf;  // c(0,0) of the 1-based recurrence
-    // sweep-order store: lane-major within a step, H contiguous floats per lane
-    float *__restrict__ zl = Z + ((int64_t)wave * 64 + lane) * H;
+    // sweep-order store: lane-major within a step, H contiguous floats (or
+    // W2 move words) per lane
+    float *__restrict__ zl = MODE == 0 ? Z + ((int64_t)wave * 64 + lane) * H : nullptr;
     const int64_t zstep = (int64_t)G * 64 * H;
+    unsigned *__restrict__ ml = MODE != 0 ? M + ((int64_t)wave * 64 + lane) * W2 : nullptr;
+    const int64_t mstep = (int64_t)G * 64 * W2;
+    const int rlast = geo.na - 1 - rbase;  // the row of c(n, m) in this lane (if 0 <= rlast < H)
 
     // One step: column s - skew of this lane's H rows, from the previous
     // column Oi into Oo (two steps per iteration ping-pong the arrays).
@@ -98,25 +129,49 @@ __global__ __launch_bounds__(64 * G) void k_cost_matrix(const float *__restrict_
         const int c = s - skew;
         float diag = diag_in, up = up_in;
         const int off = rbase - c;
+        unsigned mw[W2];
+#pragma unroll
+        for (int k = 0; k < W2; ++k) mw[k] = 0u;
 #pragma unroll
         for (int h = 0; h < H; ++h) {
             float xe = x[h];
             if constexpr (BANDED) xe = (unsigned)(off + h + band) > (unsigned)(2 * band) ? kBig : xe;
             const float d = xe - yv;
             const float v = fmaf(d, d, min3f(diag, up, Oi[h]));
+            if constexpr (MODE == 1) mw[h / 16] |= move_code(diag, up, Oi[h]) << (2 * (h % 16));
+            if constexpr (MODE == 2) mw[h / 16] |= move_code(diag, Oi[h], up) << (2 * (h % 16));
             diag = Oi[h];
             up = v;
             Oo[h] = v;
         }
-        if constexpr (H % 4 == 0) {
+        if constexpr (MODE == 0) {
+            if constexpr (H % 4 == 0) {
 #pragma unroll
-            for (int h = 0; h < H; h += 4)
-                *reinterpret_cast<float4 *>(zl + h) = make_float4(Oo[h], Oo[h + 1], Oo[h + 2], Oo[h + 3]);
+                for (int h = 0; h < H; h += 4)
+                    *reinterpret_cast<float4 *>(zl + h) = make_float4(Oo[h], Oo[h + 1], Oo[h + 2], Oo[h + 3]);
+            } else {
+#pragma unroll
+                for (int h = 0; h < H; ++h) zl[h] = Oo[h];
+            }
+            zl += zstep;
         } else {
+            if constexpr (W2 == 1) {
+                ml[0] = mw[0];
+            } else if constexpr (W2 == 2) {
+                *reinterpret_cast<uint2 *>(ml) = make_uint2(mw[0], mw[1]);
+            } else {
 #pragma unroll
-            for (int h = 0; h < H; ++h) zl[h] = Oo[h];
+                for (int k = 0; k < W2; k += 4)
+                    *reinterpret_cast<uint4 *>(ml + k) = make_uint4(mw[k], mw[k + 1], mw[k + 2], mw[k + 3]);
+            }
+            ml += mstep;
+            if (c == geo.nb - 1 && static_cast<unsigned>(rlast) < static_cast<unsigned>(H)) {
+                float v = Oo[0];
+#pragma unroll
+                for (int h = 1; h < H; ++h) v = rlast == h ? Oo[h] : v;
+                *cost = v;
+            }
         }
-        zl += zstep;
         const float bottom = Oo[H - 1];
         if constexpr (G > 1) {
             if (lane == 63 && wave < G - 1) ring[wave][c & (kPRing - 1)] = bottom;
@@ -168,9 +223,11 @@ __global__ __launch_bounds__(64 * G) void k_cost_matrix(const float *__restrict_
 // produced backwards and reversed in place at the end.
 typedef unsigned MoveWords __attribute__((ext_vector_type(16)));  // register-indexed reads need >= 16 elements
 
-__global__ __launch_bounds__(64) void k_backtrack(const float *__restrict__ Z, const PathGeom geo, int n, int m,
-                                                  int *__restrict__ path, int64_t *__restrict__ out_len,
-                                                  float *__restrict__ out_cost) {
+// The walk itself: tile_moves(i0, j0, mw) fills the moves of the tile with
+// bottom-right corner (i0+63, j0+63) (row i0 + lane in each lane); returns
+// the path length.
+template <class TileMoves>
+__device__ __forceinline__ int64_t walk_back(int n, int m, int *__restrict__ path, TileMoves tile_moves) {
     const int lane = threadIdx.x;
     int i = n - 1, j = m - 1;  // current cell (wave-uniform)
     int pi = i, pj = j;        // lane kk holds cell kbase + kk until the flush
@@ -178,33 +235,8 @@ __global__ __launch_bounds__(64) void k_backtrack(const float *__restrict__ Z, c
     int kk = 1;
     while (i > 0 || j > 0) {
         const int i0 = i - 63, j0 = j - 63;
-        const int r = i0 + lane;
-        const int rc = r < 0 ? 0 : r;
-        // zindex(rr, cc) = zindex(rr, 0) + cc*S: a per-lane base plus a
-        // wave-uniform offset per tile column, whichever series the rows are
-        const int64_t S = (int64_t)geo.G * 64 * geo.H;
-        const float *__restrict__ zr = Z + (geo.swap ? rc * S : zindex(geo, rc, 0));
-        float v[64];
-        if (geo.swap) {
-#pragma unroll
-            for (int q = 0; q < 64; ++q) v[q] = zr[zindex(geo, j0 + q < 0 ? 0 : j0 + q, 0)];
-        } else {
-#pragma unroll
-            for (int q = 0; q < 64; ++q) v[q] = zr[(j0 + q < 0 ? 0 : j0 + q) * S];
-        }
-#pragma unroll
-        for (int q = 0; q < 64; ++q) v[q] = (r < 0 || j0 + q < 0) ? kInf : v[q];
         MoveWords mw = {};
-        float diag = lane_shift_down(v[0], kInf);
-#pragma unroll
-        for (int q = 1; q < 64; ++q) {
-            const float up = lane_shift_down(v[q], kInf), left = v[q - 1];
-            unsigned code = (diag <= up && diag <= left) ? 3u : (up <= left ? 1u : 2u);
-            code = r == 0 ? (j0 + q == 0 ? 0u : 2u) : (j0 + q == 0 ? 1u : code);  // C's first row / column
-            code = lane == 0 ? 0u : code;                                         // the tile's first row
-            mw[q >> 4] |= code << (2 * (q & 15));
-            diag = up;
-        }
+        tile_moves(i0, j0, mw);
         int ta = 63, tb = 63;
         for (;;) {
             const unsigned word = mw[tb >> 4];
@@ -241,10 +273,81 @@ __global__ __launch_bounds__(64) void k_backtrack(const float *__restrict__ Z, c
         path[2 * q] = a0;
         path[2 * q + 1] = a1;
     }
+    return k;
+}
+
+// A move with the walk's edge rules: on C's first row only (i, j-1) and on
+// its first column only (i-1, j) exist (the others are the +inf border; the
+// rule also keeps the walk inside the matrix when costs overflow or are NaN);
+// 0 (leave the tile) on the tile's first row and at the origin.
+__device__ __forceinline__ unsigned edge_rules(unsigned code, int r, int jc) {
+    code = r == 0 ? (jc == 0 ? 0u : 2u) : (jc == 0 ? 1u : code);
+    return threadIdx.x == 0 ? 0u : code;
+}
+
+// Walk from stored costs: the wavefront decides every cell's move of the tile
+// in parallel (the row above arrives by DPP).
+__global__ __launch_bounds__(64) void k_backtrack(const float *__restrict__ Z, const PathGeom geo, int n, int m,
+                                                  int *__restrict__ path, int64_t *__restrict__ out_len,
+                                                  float *__restrict__ out_cost) {
+    const int lane = threadIdx.x;
+    const int64_t k = walk_back(n, m, path, [&](int i0, int j0, MoveWords &mw) {
+        const int r = i0 + lane;
+        const int rc = r < 0 ? 0 : r;
+        // zindex(rr, cc) = zindex(rr, 0) + cc*S: a per-lane base plus a
+        // wave-uniform offset per tile column, whichever series the rows are
+        const int64_t S = (int64_t)geo.G * 64 * geo.H;
+        const float *__restrict__ zr = Z + (geo.swap ? rc * S : zindex(geo, rc, 0));
+        float v[64];
+        if (geo.swap) {
+#pragma unroll
+            for (int q = 0; q < 64; ++q) v[q] = zr[zindex(geo, j0 + q < 0 ? 0 : j0 + q, 0)];
+        } else {
+#pragma unroll
+            for (int q = 0; q < 64; ++q) v[q] = zr[(j0 + q < 0 ? 0 : j0 + q) * S];
+        }
+#pragma unroll
+        for (int q = 0; q < 64; ++q) v[q] = (r < 0 || j0 + q < 0) ? kInf : v[q];
+        float diag = lane_shift_down(v[0], kInf);
+#pragma unroll
+        for (int q = 1; q < 64; ++q) {
+            const float up = lane_shift_down(v[q], kInf), left = v[q - 1];
+            mw[q >> 4] |= edge_rules(move_code(diag, up, left), r, j0 + q) << (2 * (q & 15));
+            diag = up;
+        }
+    });
     if (lane == 0) {
         *out_len = k;
         *out_cost = cell_at(Z, geo, n - 1, m - 1);
     }
+}
+
+// Walk from the moves the sweep stored (2 bits per cell in its layout).
+__global__ __launch_bounds__(64) void k_backtrack_moves(const unsigned *__restrict__ M, const PathGeom geo, int n,
+                                                        int m, int *__restrict__ path, int64_t *__restrict__ out_len) {
+    const int lane = threadIdx.x;
+    const int64_t k = walk_back(n, m, path, [&](int i0, int j0, MoveWords &mw) {
+        const int r = i0 + lane;
+        const int rc = r < 0 ? 0 : r;
+        // mindex(rr, cc) = mindex(rr, 0) + cc*S2, as for the costs
+        const int64_t S2 = (int64_t)geo.G * 64 * ((geo.H + 15) >> 4);
+        unsigned w[64];
+        if (geo.swap) {  // caller row i0 + lane is sweep column rc; column j0 + q is sweep row j0 + q
+#pragma unroll
+            for (int q = 0; q < 64; ++q) {
+                const int rr = j0 + q < 0 ? 0 : j0 + q;
+                w[q] = M[mindex(geo, rr, 0) + rc * S2] >> mshift(geo, rr);
+            }
+        } else {
+            const unsigned *__restrict__ mr = M + mindex(geo, rc, 0);
+            const int sh = mshift(geo, rc);
+#pragma unroll
+            for (int q = 0; q < 64; ++q) w[q] = mr[(j0 + q < 0 ? 0 : j0 + q) * S2] >> sh;
+        }
+#pragma unroll
+        for (int q = 1; q < 64; ++q) mw[q >> 4] |= edge_rules(w[q] & 3u, r, j0 + q) << (2 * (q & 15));
+    });
+    if (lane == 0) *out_len = k;
 }
 
 // C[i*m + j] = c(i+1, j+1): one thread per element, stores coalesced.
@@ -256,16 +359,30 @@ __global__ __launch_bounds__(256) void k_row_major(const float *__restrict__ Z, 
     C[e] = cell_at(Z, geo, i, j);
 }
 
-template <int H, int G>
-void launch_cost_matrix(bool banded, const float *a, const float *b, const PathGeom &g, int band, float *Z,
-                        hipStream_t s) {
+template <int H, int G, int MODE>
+void launch_cost_mode(bool banded, const float *a, const float *b, const PathGeom &g, int band, float *Z,
+                      unsigned *M, float *cost, hipStream_t s) {
     if (banded)
-        hipLaunchKernelGGL((k_cost_matrix<H, G, true>), dim3(1), dim3(64 * G), 0, s, a, b, g, band, Z);
+        hipLaunchKernelGGL((k_cost_matrix<H, G, true, MODE>), dim3(1), dim3(64 * G), 0, s, a, b, g, band, Z, M, cost);
     else
-        hipLaunchKernelGGL((k_cost_matrix<H, G, false>), dim3(1), dim3(64 * G), 0, s, a, b, g, band, Z);
+        hipLaunchKernelGGL((k_cost_matrix<H, G, false, MODE>), dim3(1), dim3(64 * G), 0, s, a, b, g, band, Z, M,
+                           cost);
 }
 
-using CostFn = void (*)(bool, const float *, const float *, const PathGeom &, int, float *, hipStream_t);
+// Z != nullptr: store costs; else the moves into M and c(n, m) into *cost.
+template <int H, int G>
+void launch_cost_matrix(bool banded, const float *a, const float *b, const PathGeom &g, int band, float *Z,
+                        unsigned *M, float *cost, hipStream_t s) {
+    if (Z)
+        launch_cost_mode<H, G, 0>(banded, a, b, g, band, Z, M, cost, s);
+    else if (g.swap)
+        launch_cost_mode<H, G, 2>(banded, a, b, g, band, Z, M, cost, s);
+    else
+        launch_cost_mode<H, G, 1>(banded, a, b, g, band, Z, M, cost, s);
+}
+
+using CostFn = void (*)(bool, const float *, const float *, const PathGeom &, int, float *, unsigned *, float *,
+                        hipStream_t);
 struct PathShape {
     int H, G;
     CostFn fn;
@@ -294,6 +411,21 @@ struct DevBuf {
         if (p) (void)hipFree(p);
     }
 };
+
+// Move buffers kept between calls, one per device, grown to the largest pair
+// so far up to kPathKeepBytes (larger ones are allocated for the call and
+// freed); a call holds the lock of the cache until its stream has finished.
+constexpr size_t kPathKeepBytes = size_t(1) << 30;
+constexpr int kPathDevices = 64;
+struct PathCache {
+    std::mutex lock;
+    void *p[kPathDevices] = {};
+    size_t bytes[kPathDevices] = {};
+};
+PathCache &path_cache() {
+    static PathCache c;
+    return c;
+}
 
 }  // namespace
 }  // namespace dtwmi
@@ -325,22 +457,69 @@ extern "C" int dtw_path(const float *x, int32_t n, const float *y, int32_t m, in
     const int diff = g.nb - g.na;
     const int band = window < 0 ? -1 : (window > diff ? window : diff);
     const bool banded = band >= 0 && band < g.nb - 1;  // a wider band admits every cell
-    const int64_t zbytes = steps * g.G * g.H * 64 * (int64_t)sizeof(float);
-
     hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = hipSuccess;
+    if (!C) {
+        // moves only: 2 bits a cell in a kept buffer, the length and cost after them
+        const size_t mbytes = ((size_t)steps * g.G * 64 * ((g.H + 15) / 16) * sizeof(unsigned) + 255) / 256 * 256;
+        const size_t need = mbytes + 256;
+        int dev = 0;
+        if ((e = hipGetDevice(&dev)) != hipSuccess) return path_err(DTW_ERR_HIP, "hipGetDevice", e);
+        if (dev < 0 || dev >= kPathDevices) return path_err(DTW_ERR_UNSUPPORTED, "device index out of range");
+        PathCache &pc = path_cache();
+        std::lock_guard<std::mutex> guard(pc.lock);
+        DevBuf once;
+        char *buf = nullptr;
+        if (need > kPathKeepBytes) {
+            if ((e = hipMalloc(&once.p, need)) != hipSuccess)
+                return path_err(DTW_ERR_OUT_OF_MEMORY, "move buffer allocation", e);
+            buf = static_cast<char *>(once.p);
+        } else {
+            if (pc.bytes[dev] < need) {
+                if (pc.p[dev]) (void)hipFree(pc.p[dev]);  // the previous call's stream has finished
+                pc.p[dev] = nullptr;
+                pc.bytes[dev] = 0;
+                if ((e = hipMalloc(&pc.p[dev], need)) != hipSuccess)
+                    return path_err(DTW_ERR_OUT_OF_MEMORY, "move buffer allocation", e);
+                pc.bytes[dev] = need;
+            }
+            buf = static_cast<char *>(pc.p[dev]);
+        }
+        unsigned *M = reinterpret_cast<unsigned *>(buf);
+        int64_t *d_len = reinterpret_cast<int64_t *>(buf + mbytes);
+        float *d_cost = reinterpret_cast<float *>(buf + mbytes + 64);
+        // on a failure after a launch, wait for the stream before the buffer is released
+        auto failed = [&](const char *what) {
+            const int rc = path_err(DTW_ERR_HIP, what, e);
+            (void)hipStreamSynchronize(s);
+            return rc;
+        };
+        shape->fn(banded, g.swap ? y : x, g.swap ? x : y, g, band, nullptr, M, d_cost, s);
+        if ((e = hipGetLastError()) != hipSuccess) return failed("cost-matrix kernel launch");
+        hipLaunchKernelGGL(k_backtrack_moves, dim3(1), dim3(64), 0, s, M, g, n, m, path, d_len);
+        if ((e = hipGetLastError()) != hipSuccess) return failed("backtrack kernel launch");
+        e = hipMemcpyAsync(path_len, d_len, sizeof(int64_t), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(cost, d_cost, sizeof(float), hipMemcpyDeviceToHost, s);
+        if (e != hipSuccess) return failed("path result");
+        if ((e = hipStreamSynchronize(s)) != hipSuccess) return path_err(DTW_ERR_HIP, "path result", e);
+        return DTW_OK;
+    }
+
+    // the cost matrix asked for: keep every cell's cost, decide the moves from them
+    const int64_t zbytes = steps * g.G * g.H * 64 * (int64_t)sizeof(float);
     DevBuf z, small;
-    hipError_t e = hipMalloc(&z.p, static_cast<size_t>(zbytes));
+    e = hipMalloc(&z.p, static_cast<size_t>(zbytes));
     if (e != hipSuccess) return path_err(DTW_ERR_OUT_OF_MEMORY, "cost matrix allocation", e);
     if ((e = hipMalloc(&small.p, 256)) != hipSuccess) return path_err(DTW_ERR_OUT_OF_MEMORY, "allocation", e);
     float *Z = static_cast<float *>(z.p);
     int64_t *d_len = static_cast<int64_t *>(small.p);
     float *d_cost = reinterpret_cast<float *>(static_cast<char *>(small.p) + 64);
 
-    shape->fn(banded, g.swap ? y : x, g.swap ? x : y, g, band, Z, s);
+    shape->fn(banded, g.swap ? y : x, g.swap ? x : y, g, band, Z, nullptr, nullptr, s);
     if ((e = hipGetLastError()) != hipSuccess) return path_err(DTW_ERR_HIP, "cost-matrix kernel launch", e);
     hipLaunchKernelGGL(k_backtrack, dim3(1), dim3(64), 0, s, Z, g, n, m, path, d_len, d_cost);
     if ((e = hipGetLastError()) != hipSuccess) return path_err(DTW_ERR_HIP, "backtrack kernel launch", e);
-    if (C) {
+    {
         const int64_t blocks = ((int64_t)n * m + 255) / 256;
         if (blocks > INT32_MAX) return path_err(DTW_ERR_UNSUPPORTED, "cost matrix too large for C");
         hipLaunchKernelGGL(k_row_major, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, Z, g, n, m, C);

@@ -74,6 +74,9 @@ def test_integer_series_path_is_the_oracle_path(n, m, window):
     assert p == [tuple(c) for c in p_ref]
     if want_C:
         np.testing.assert_array_equal(C.astype(np.float64), Cref[1:, 1:])
+        # without the matrix the sweep stores only the moves (2 bits a cell): the same walk
+        p2, cost2, _ = _run(B, x, y, window)
+        assert p2 == p and cost2 == cost
 
 
 @pytest.mark.parametrize("n,m", [(1, 3), (40, 40), (64, 200), (333, 129), (1000, 1000), (2500, 2100)])
@@ -149,4 +152,16 @@ def test_repeated_calls_and_caller_stream():
     for _ in range(3):
         p, cost = B.warping_path(dx, dy, 11, path_out=buf, stream=s)
         assert [tuple(map(int, r)) for r in p.cpu().numpy()] == [tuple(c) for c in ref[0]]
+        assert cost == ref[1]
+
+
+def test_move_buffer_kept_between_calls_of_changing_size():
+    # the moves-only form keeps its buffer between calls and grows it: calls
+    # of increasing, then decreasing size, each checked against the oracle
+    B = _gpu()
+    for k, (n, m) in enumerate([(200, 300), (2600, 2500), (90, 1400), (3100, 3300), (64, 65)]):
+        x, y = _int_series(500 + k, n, m)
+        p, cost, _ = _run(B, x, y, 40)
+        ref = opath.warping_path(x, y, 40)
+        assert p == [tuple(c) for c in ref[0]], (n, m)
         assert cost == ref[1]
