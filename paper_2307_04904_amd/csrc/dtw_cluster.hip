@@ -122,6 +122,93 @@ __global__ __launch_bounds__(kRowBlock) void k_row_cluster_sums(const float *__r
             if (J < K) P[((int64_t)split * N + i) * K + J] = acc[J / 16][J % 16];
 }
 
+// Each entry of D once: workgroup (SC, SR) of kSilR wavefronts covers rows
+// [256 SR, 256 SR + 256) (wavefront w: row block I = 4 SR + w, 64 rows) and
+// columns [512 SC, 512 SC + 512) (kSilT column tiles); a tile (I, J) is
+// processed only for J >= I, and on the diagonal (J == I) only for i < j, so
+// every condensed entry D(i, j), i < j, is read by exactly one wavefront.  It
+// adds D(i, j) both to row i's sum for cluster labels[j] and to row j's sum
+// for cluster labels[i]:
+//  * lane = column j: the tile is loaded row by row (coalesced: 64
+//    consecutive entries of row i of the condensed triangle) into registers,
+//    and each lane adds its column's values over the tile's rows (label of
+//    the row wave-uniform); the four wavefronts' column sums of the tile are
+//    then added in wavefront order through LDS and written to
+//    Pcol[SR][J][j] (per super-row SR);
+//  * lane = row i: the tile goes through LDS to be read transposed, and each
+//    lane adds its row's values over the tile's columns, in registers across
+//    the kSilT tiles, written once to Prow[SC][J][i] (per super-column SC).
+// (Cluster-major partials: the per-series kernel reads each cluster's sums
+// of consecutive series as one coalesced run.)
+// The per-series sums then add the Prow and Pcol partials in a fixed order,
+// so D is read once from HBM and the results repeat bit for bit.  K <= 16.
+constexpr int kSilR = 4;   // row blocks (wavefronts) per workgroup
+constexpr int kSilT = 8;   // column tiles per workgroup
+constexpr int kSilRows = kSilR * kRowBlock, kSilCols = kSilT * kRowBlock;
+// the super-tiles (SR, SC) holding a tile on or above the diagonal
+__host__ __device__ constexpr bool sil_launched(int SR, int SC) { return kSilCols * SC + kSilCols - 1 >= kSilRows * SR; }
+__host__ __device__ constexpr int sil_first_sc(int SR) { return kSilRows * SR / kSilCols; }
+__host__ __device__ constexpr int sil_last_sr(int SC) { return (kSilCols * SC + kSilCols - 1) / kSilRows; }
+
+__global__ __launch_bounds__(64 * kSilR) void k_cluster_sums_once(const float *__restrict__ D, int N,
+                                                                  const int *__restrict__ labels, int K,
+                                                                  double *__restrict__ Prow,
+                                                                  double *__restrict__ Pcol) {
+    __shared__ float tile[kSilR][kRowBlock][kRowBlock + 1];  // a wavefront's tile; reused for its column sums
+    const int SC = blockIdx.x, SR = blockIdx.y;
+    if (!sil_launched(SR, SC)) return;  // below the diagonal: no tile with J >= I (uniform per workgroup)
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;  // w: wave-uniform
+    const int I = kSilR * SR + w, i0 = I * kRowBlock;
+    Acc16 accr[1] = {Acc16{}};
+#pragma unroll 1
+    for (int t = 0; t < kSilT; ++t) {
+        const int J = kSilT * SC + t, j0 = J * kRowBlock;
+        const bool valid = J >= I && i0 < N && j0 < N;  // wave-uniform
+        Acc16 accc[1] = {Acc16{}};
+        const int j = j0 + lane;
+        if (valid) {
+            float v[kRowBlock];  // all 64 rows of the tile in flight at once
+#pragma unroll
+            for (int r = 0; r < kRowBlock; ++r) {
+                const int ir = i0 + r;
+                v[r] = (ir < j && j < N) ? D[condensed_index(ir, j, N)] : 0.0f;
+            }
+#pragma unroll
+            for (int r = 0; r < kRowBlock; ++r) {
+                const int ir = i0 + r;
+                acc_add<1>(accc, ir < N ? labels[ir] : 0, (double)v[r]);  // wave-uniform label
+                tile[w][r][lane] = v[r];
+            }
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll 8
+            for (int c = 0; c < kRowBlock; ++c) {
+                const int jc = j0 + c;
+                acc_add<1>(accr, jc < N ? labels[jc] : 0, (double)tile[w][lane][c]);
+            }
+            __builtin_amdgcn_wave_barrier();  // the transposed reads are done before the tile is reused
+        }
+        // column sums of the tile: this wavefront's into its LDS region, then added in wavefront order
+        double *red = reinterpret_cast<double *>(&tile[w][0][0]);  // [16][64]
+#pragma unroll
+        for (int k = 0; k < 16; ++k) red[k * kRowBlock + lane] = accc[0][k];
+        __syncthreads();
+        if (j0 < N) {
+            for (int k = w; k < K; k += kSilR) {
+                double s = 0.0;
+#pragma unroll
+                for (int q = 0; q < kSilR; ++q) s += reinterpret_cast<const double *>(&tile[q][0][0])[k * kRowBlock + lane];
+                if (j < N) Pcol[((int64_t)SR * K + k) * N + j] = s;
+            }
+        }
+        __syncthreads();  // the sums are read before the next tile overwrites the regions
+    }
+    const int i = i0 + lane;
+    if (i < N)
+#pragma unroll
+        for (int k = 0; k < 16; ++k)
+            if (k < K) Prow[((int64_t)SC * K + k) * N + i] = accr[0][k];
+}
+
 // Fixed-order tree sum of one workgroup's values into out.
 __device__ __forceinline__ void block_sum(double v, double *red, double *out) {
     red[threadIdx.x] = v;
@@ -133,11 +220,16 @@ __device__ __forceinline__ void block_sum(double v, double *red, double *out) {
     if (threadIdx.x == 0) *out = red[0];
 }
 
-// s(i) from the cluster sums; per-workgroup partial sums of s.
+// s(i) from the cluster sums; per-workgroup partial sums of s.  P holds
+// `splits` row-sum partials per series (k_row_cluster_sums); or, with Pcol,
+// the partials of k_cluster_sums_once: the row sums of every super-column
+// from sil_first_sc on (the super-tiles on or above the diagonal) in P, then
+// the column sums of super-rows 0 .. sil_last_sr in Pcol.
 __global__ __launch_bounds__(kReduce) void k_silhouette_rows(const double *__restrict__ P, int splits, int N, int K,
                                                              const int *__restrict__ labels,
                                                              const int *__restrict__ sizes, float *__restrict__ s_out,
-                                                             double *__restrict__ partial) {
+                                                             double *__restrict__ partial,
+                                                             const double *__restrict__ Pcol, int n_sr) {
     __shared__ double red[kReduce];
     const int i = blockIdx.x * kReduce + threadIdx.x;
     double s = 0.0;
@@ -145,9 +237,18 @@ __global__ __launch_bounds__(kReduce) void k_silhouette_rows(const double *__res
         const int A = labels[i];
         if (sizes[A] > 1) {
             double a = 0.0, b = __builtin_huge_val();
+            const int sp0 = Pcol ? sil_first_sc(i / kSilRows) : 0;
+            const int sr1 = Pcol ? min(n_sr - 1, sil_last_sr(i / kSilCols)) : -1;
             for (int J = 0; J < K; ++J) {
                 double sum = 0.0;
-                for (int sp = 0; sp < splits; ++sp) sum += P[((int64_t)sp * N + i) * K + J];
+                if (Pcol) {  // unrolled so that the loads of several partials are in flight together
+#pragma unroll 8
+                    for (int sp = sp0; sp < splits; ++sp) sum += P[((int64_t)sp * K + J) * N + i];
+#pragma unroll 8
+                    for (int sr = 0; sr <= sr1; ++sr) sum += Pcol[((int64_t)sr * K + J) * N + i];
+                } else {
+                    for (int sp = 0; sp < splits; ++sp) sum += P[((int64_t)sp * N + i) * K + J];
+                }
                 if (J == A)
                     a = sum / (double)(sizes[A] - 1);
                 else if (sizes[J] > 0)
@@ -262,17 +363,23 @@ int dtw_silhouette(const float *D, int32_t N, const int32_t *labels, int32_t K, 
     if (std::count_if(sizes.begin(), sizes.end(), [](int32_t z) { return z > 0; }) < 2)
         return set_error(DTW_ERR_INVALID_ARG, "the silhouette needs at least two non-empty clusters");
 
-    // Column tiles split so that there are ~2048 workgroups of one wavefront,
-    // each with at least one tile (more splits cost more in the per-series
-    // reduction of the partial sums than they gain here).
+    // K <= 16: each entry of D read once (k_cluster_sums_once; partials per
+    // super-column and super-row).  More clusters: every entry read for both
+    // its rows, the column tiles split so that there are ~2048 workgroups of
+    // one wavefront, each with at least one tile (more splits cost more in the
+    // per-series reduction of the partial sums than they gain here).
+    const bool once = K <= 16;
     const int row_blocks = (N + kRowBlock - 1) / kRowBlock;
     const int n_tiles = row_blocks;
     const int target_groups = 2048;
-    const int splits = std::max(1, std::min(n_tiles, (target_groups + row_blocks - 1) / row_blocks));
+    const int n_sc = (N + kSilCols - 1) / kSilCols, n_sr = (N + kSilRows - 1) / kSilRows;
+    const int splits = once ? n_sc : std::max(1, std::min(n_tiles, (target_groups + row_blocks - 1) / row_blocks));
     const int tiles_per_split = (n_tiles + splits - 1) / splits;
     const int red_blocks = (N + kReduce - 1) / kReduce;
     const size_t o_sizes = 0, o_P = 256, bytes_P = (size_t)splits * N * K * sizeof(double);
-    const size_t o_part = o_P + ((bytes_P + 255) / 256) * 256;
+    const size_t bytes_Pc = once ? (size_t)n_sr * N * K * sizeof(double) : 0;
+    const size_t o_Pc = o_P + ((bytes_P + 255) / 256) * 256;
+    const size_t o_part = o_Pc + ((bytes_Pc + 255) / 256) * 256;
     const size_t o_out = o_part + ((red_blocks * sizeof(double) + 255) / 256) * 256;
     Scratch w;
     hipError_t e = hipMalloc(&w.p, o_out + 256);
@@ -280,20 +387,20 @@ int dtw_silhouette(const float *D, int32_t N, const int32_t *labels, int32_t K, 
     char *base = static_cast<char *>(w.p);
     int *d_sizes = reinterpret_cast<int *>(base + o_sizes);
     double *d_P = reinterpret_cast<double *>(base + o_P);
+    double *d_Pc = once ? reinterpret_cast<double *>(base + o_Pc) : nullptr;
     double *d_part = reinterpret_cast<double *>(base + o_part);
     double *d_out = reinterpret_cast<double *>(base + o_out);
     e = hipMemcpyAsync(d_sizes, sizes.data(), K * sizeof(int32_t), hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return hip_err(e, "hipMemcpy (cluster sizes)");
     static_assert(kSilhouetteMaxK <= 64, "four vectors of 16 accumulators");
-    if (K <= 16)
-        hipLaunchKernelGGL((k_row_cluster_sums<1, 64>), dim3(row_blocks, splits), dim3(kRowBlock), 0, s, D, N, labels,
-                           K, tiles_per_split, d_P);
+    if (once)
+        hipLaunchKernelGGL(k_cluster_sums_once, dim3(n_sc, n_sr), dim3(64 * kSilR), 0, s, D, N, labels, K, d_P, d_Pc);
     else
         hipLaunchKernelGGL((k_row_cluster_sums<4, 16>), dim3(row_blocks, splits), dim3(kRowBlock), 0, s, D, N, labels,
                            K, tiles_per_split, d_P);
     if ((e = hipGetLastError()) != hipSuccess) return hip_err(e, "row-sum kernel launch");
     hipLaunchKernelGGL(k_silhouette_rows, dim3(red_blocks), dim3(kReduce), 0, s, d_P, splits, N, K, labels, d_sizes,
-                       s_out, d_part);
+                       s_out, d_part, d_Pc, n_sr);
     if ((e = hipGetLastError()) != hipSuccess) return hip_err(e, "silhouette kernel launch");
     hipLaunchKernelGGL(k_sum_by_key, dim3(1), dim3(kReduce), 0, s, d_part, red_blocks, nullptr, 1, d_out);
     if ((e = hipGetLastError()) != hipSuccess) return hip_err(e, "reduction kernel launch");
