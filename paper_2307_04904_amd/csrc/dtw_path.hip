@@ -137,9 +137,13 @@ __global__ __launch_bounds__(64 * G) void k_cost_matrix(const float *__restrict_
             float xe = x[h];
             if constexpr (BANDED) xe = (unsigned)(off + h + band) > (unsigned)(2 * band) ? kBig : xe;
             const float d = xe - yv;
-            const float v = fmaf(d, d, min3f(diag, up, Oi[h]));
-            if constexpr (MODE == 1) mw[h / 16] |= move_code(diag, up, Oi[h]) << (2 * (h % 16));
-            if constexpr (MODE == 2) mw[h / 16] |= move_code(diag, Oi[h], up) << (2 * (h % 16));
+            const float mn = min3f(diag, up, Oi[h]);
+            const float v = fmaf(d, d, mn);
+            // the move from the minimum already at hand: the diagonal if it is
+            // the minimum, else (i-1, j) if that is, else (i, j-1) -- the order
+            // of move_code's ties
+            if constexpr (MODE == 1) mw[h / 16] |= (mn == diag ? 3u : (mn == up ? 1u : 2u)) << (2 * (h % 16));
+            if constexpr (MODE == 2) mw[h / 16] |= (mn == diag ? 3u : (mn == Oi[h] ? 1u : 2u)) << (2 * (h % 16));
             diag = Oi[h];
             up = v;
             Oo[h] = v;
