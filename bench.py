@@ -293,6 +293,31 @@ def extra_workloads(dev, stream, steps):
 
     c2, _ = rate([synth.config2()], False, max(50, steps // 2))
     out["c2_1000x512_w51"] = dict(c2, description=WORKLOADS["c2"])
+    # the k-medoids step on the same data (a pair list; the planner spreads
+    # each pair over several lanes), against one pair per lane
+    ds2 = synth.config2()
+    pairs = medoid_pairs(ds2.N, MEDOIDS)
+    series2 = binding.device_series(ds2, dev)
+    km = {}
+    for ppw in (0, 64):
+        o = torch.full((len(pairs),), float("nan"), device=dev)
+        plan = binding.PairPlan(series2, ds2.lengths, ds2.offsets, ds2.window, pairs, o, timing=True,
+                                pairs_per_wave=ppw)
+        step, g = make_step(plan, stream, False)
+        ms, _ = time_steps(step, stream, 200, 20)
+        kms = []
+        for _ in range(5):
+            plan.execute(stream)
+            kms.append(plan.last_kernel_ms())
+        desc = plan.describe()
+        del g
+        plan.destroy()
+        km[ppw] = (ms, statistics.mean(kms), desc["lane_groups"][0]["pairs_per_wave"])
+    out["c2m_kmedoids_step"] = {
+        "pairs": len(pairs), "ms_per_step": round(km[0][0], 4), "kernel_ms": round(km[0][1], 4),
+        "pairs_per_wave": km[0][2], "one_pair_per_lane_ms_per_step": round(km[64][0], 4),
+        "one_pair_per_lane_kernel_ms": round(km[64][1], 4), "speedup_kernel": round(km[64][1] / km[0][1], 2),
+        "description": WORKLOADS["c2m"]}
     c4, c4_outs = rate(synth.config4(), True, 20)
     c4["ratio_to_equal_size_rate"] = round(c4["gcups"] / c2["gcups"], 4)
     out["c4_batched_64_datasets"] = dict(c4, description=WORKLOADS["c4"], timing="hip graph replays")
