@@ -356,7 +356,7 @@ def main(argv=None):
     ap.add_argument("--accum", default="auto", choices=["auto", "plain", "rebased", "kahan", "fp64"])
     ap.add_argument("--rows-per-lane", type=int, default=0,
                     help="force the strip / cyclic rows per lane (0 = cost model)")
-    ap.add_argument("--pairs-per-wave", type=int, default=0, choices=[0, 2, 4, 8, 16, 64],
+    ap.add_argument("--pairs-per-wave", type=int, default=0, choices=[0, 2, 4, 5, 8, 16, 64],
                     help="force the lane-band kernel's pairs per wavefront (0 = automatic)")
     ap.add_argument("--silhouette", type=int, default=0, metavar="K",
                     help="also time dtw_silhouette on the computed matrix with K seeded random clusters")

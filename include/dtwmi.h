@@ -116,14 +116,15 @@ typedef struct dtw_options {
                               pair returns DTW_ERR_UNSUPPORTED.  Ignored by LANE. */
     int32_t pairs_per_wave; /* LANE kernel: pairs per wavefront.  0 = automatic: 64 (one pair
                               per lane) when that gives every SIMD of the device at least two
-                              wavefronts, else 16, 8, 4 or 2 by an estimate of the time (each
-                              pair's band row spread over 4, 8, 16 or 32 lanes; PLAIN sums only;
-                              same results bit for bit).  64, 16, 8, 4 or 2 forces it; a split
-                              the band width has no instance for (3 to 16 band cells per lane,
-                              at most 8 with 4 pairs per wavefront and 4 with 2) or REBASED sums
-                              returns DTW_ERR_UNSUPPORTED.  Other values are
-                              DTW_ERR_INVALID_ARG.  Ignored by WAVE and CYCLIC and by
-                              dtw_pairwise_noalloc (which runs 64). */
+                              wavefronts, else 16, 8, 5, 4 or 2 by an estimate of the time (each
+                              pair's band row spread over 4, 8, 12, 16 or 32 lanes; with 12 the
+                              last 4 lanes idle; PLAIN sums only; same results bit for bit).
+                              64, 16, 8, 5, 4 or 2 forces it; a split the band width has no
+                              instance for (3 to 16 band cells per lane, at most 11 with 5 pairs
+                              per wavefront, 8 with 4 and 4 with 2) or REBASED sums returns
+                              DTW_ERR_UNSUPPORTED.  Other values are DTW_ERR_INVALID_ARG.
+                              Ignored by WAVE and CYCLIC and by dtw_pairwise_noalloc (which
+                              runs 64). */
     void *stream;   /* hipStream_t used by dtw_pairwise_ex and dtw_pairs; NULL = default stream */
     /* Output sub-range: only the entries k with k_begin <= k < k_end of every
      * dataset's output are evaluated and written (the condensed index k(i,j)

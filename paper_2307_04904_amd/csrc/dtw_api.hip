@@ -196,27 +196,29 @@ void split_lane_items(const std::vector<LaneItem> &tiles, int P, std::vector<Lan
 std::vector<int> lane_split_candidates(int W, bool rebased) {
     std::vector<int> c{1};
     if (!rebased)
-        for (int P : {4, 8, 16, 32})
+        for (int P : {4, 8, 12, 16, 32})
             if (lane_split_supported(P, W)) c.push_back(P);
     return c;
 }
 
 // Lanes per pair of a lane-band group of 64-pair items over series of up to
 // L points: one (64 pairs per wavefront) when the items give every SIMD at
-// least two wavefronts; else the split (P = 4, 8, 16 or 32 lanes per pair,
-// items of 64/P pairs) of the smallest estimated time.  The estimate: L + P - 1
+// least two wavefronts; else the split (P = 4, 8, 12, 16 or 32 lanes per
+// pair, items of 64/P pairs) of the smallest estimated time.  The estimate: L + P - 1
 // steps, each the longer of the dependent chain through a lane (two
 // operations per cell of its w = ceil(W/P) and five for the hand-overs, ~10
 // cycles each) and the issue of the 3w + 6 instructions of every wavefront
 // sharing its SIMD (~3.3 cycles each), all wavefronts resident at once --
 // constants fitted to the 10,000 pairs of 512 points, band 103, where 8,
 // 16 and 32 lanes per pair measured 0.078, 0.069 and 0.087 ms (4 lanes would
-// hold 26 cells, past the instances).
+// hold 26 cells, past the instances); 12 lanes, added later, 0.059 against
+// 0.064 with 16 and 0.073 with 8 on one device (2,000 wavefronts: at most two
+// per SIMD instead of three).
 int lane_split_choice(int W, bool rebased, int L, const std::vector<LaneItem> &items, int simds) {
     if (rebased || (int64_t)items.size() >= 2LL * simds) return 1;
     int best = 1;
     double best_t = 0.0;
-    for (int P : {4, 8, 16, 32}) {
+    for (int P : {4, 8, 12, 16, 32}) {
         if (!lane_split_supported(P, W)) continue;
         int64_t waves = 0;
         for (const LaneItem &it : items) waves += (it.cnt + 64 / P - 1) / (64 / P);
@@ -482,8 +484,9 @@ int validate_options(const dtw_options *opt) {
     if (opt->rows_per_lane < 0 || opt->rows_per_lane > 64)
         return fail(DTW_ERR_INVALID_ARG, "rows_per_lane=%d outside 0..64", opt->rows_per_lane);
     if (opt->pairs_per_wave != 0 && opt->pairs_per_wave != 2 && opt->pairs_per_wave != 4 &&
-        opt->pairs_per_wave != 8 && opt->pairs_per_wave != 16 && opt->pairs_per_wave != 64)
-        return fail(DTW_ERR_INVALID_ARG, "pairs_per_wave=%d is not 0, 2, 4, 8, 16 or 64", opt->pairs_per_wave);
+        opt->pairs_per_wave != 5 && opt->pairs_per_wave != 8 && opt->pairs_per_wave != 16 &&
+        opt->pairs_per_wave != 64)
+        return fail(DTW_ERR_INVALID_ARG, "pairs_per_wave=%d is not 0, 2, 4, 5, 8, 16 or 64", opt->pairs_per_wave);
     if ((opt->kernel == DTW_KERNEL_CYCLIC || opt->kernel == DTW_KERNEL_LANE) &&
         (opt->accum == DTW_ACC_KAHAN || opt->accum == DTW_ACC_FP64))
         return fail(DTW_ERR_UNSUPPORTED, "the %s kernel needs AUTO, PLAIN or REBASED accumulation",
@@ -1037,7 +1040,7 @@ int plan_build(dtw_plan *plan_out, const dtw_dataset *ds, int32_t n_datasets, co
             return fail(DTW_ERR_UNSUPPORTED,
                         "pairs_per_wave=%d: no split lane-band kernel for band width %d with %s sums (it needs "
                         "PLAIN sums and 3 to %d band cells per lane)",
-                        force_ppw, W, rebased ? "rebased" : "plain", P == 32 ? 4 : (P == 16 ? 8 : 16));
+                        force_ppw, W, rebased ? "rebased" : "plain", split_max_cells(P));
         }
         LaneGroup g{W, rebased, (int64_t)lane_items.size(), 0, P};
         g.model_P = P;

@@ -27,9 +27,11 @@ hipError_t launch_rebind(SeriesSrc *src, int32_t nseries, const void *series, Da
 // once (CUs x occupancy per CU; 0 if it cannot be queried).
 int resident_blocks(const void *fn, int block);
 bool lane_width_supported(int W);
-// The split lane-band kernel (dtw_lane_split.hip): P = 4, 8, 16 or 32 lanes
-// per pair, 64/P pairs per wavefront, plain FP32 sums; items of at most 64/P
-// partners, one workgroup each.
+// The split lane-band kernel (dtw_lane_split.hip): P = 4, 8, 12, 16 or 32
+// lanes per pair, 64/P pairs per wavefront (integer division: 12 lanes give 5
+// and leave 4 lanes idle), plain FP32 sums; items of at most 64/P partners,
+// one workgroup each; 3 to split_max_cells(P) band cells per lane.
+int split_max_cells(int P);
 bool lane_split_supported(int P, int W);
 hipError_t launch_lane_split(int P, int W, const float *ws, const SeriesInfo *ser, const DatasetInfo *dsi,
                              const LaneItem *items, const LanePartner *partners, unsigned n_items,

@@ -1,5 +1,6 @@
 // Split lane-band kernel for the all-pairs DTW matrix: the band row of a pair
-// spread over P lanes, 64/P pairs per wavefront.  Evaluates Eq. (c) of the
+// spread over P lanes, 64/P pairs per wavefront (integer division; with P = 12
+// the last 4 lanes idle).  Evaluates Eq. (c) of the
 // paper ("Mathematical background") under the window rule of the
 // Introduction, for equal-length series, in plain FP32 sums: each cell with
 // the same operations as the one-pair-per-lane kernel (dtw_lane.h), so the
@@ -27,13 +28,12 @@ namespace {
 // padding).  Lane p sweeps row r = t - p at step t:
 //   new[u] = (x_r - y_{r-B+K_p+u})^2 + min3(old[u], old[u+1], new[u-1]);
 // the left value of its first cell is the last cell of row r of lane p-1,
-// computed one step earlier and received by DPP row_shr:1 at the end of that
-// step; the up value of its last cell is cell K_{p+1} of row r-1, which lane
-// p+1 computes first in this same step and hands over by DPP row_shl:1 right
-// after.  Lane 0's left and lane P-1's up are outside the band (+inf): for
-// P = 16 a group is a row of 16 lanes, whose DPP edge gives +inf by itself;
-// other P select it.  Row -1 is the initial
-// register contents (+inf but for c(0,0), the diagonal of cell (0,0)), and a
+// computed one step earlier and received by a DPP shift right at the end of
+// that step; the up value of its last cell is cell K_{p+1} of row r-1, which
+// lane p+1 computes first in this same step and hands over by a DPP shift left
+// right after.  Lane 0's left and lane P-1's up are outside the band (+inf):
+// each move raises the value a group-edge lane receives to +inf.  Row -1 is
+// the initial register contents (+inf but for c(0,0), the diagonal of cell (0,0)), and a
 // lane that has not started (r < 0) or has finished (r >= L) keeps its
 // registers, so a lane that starts reads row -1 from its right neighbour and
 // the final row stays in place.
@@ -46,34 +46,37 @@ namespace {
 template <int w>
 constexpr int split_steps() { return w <= 8 ? 16 : 8; }
 
-// Lane l gets lane l-1 (from_left) or l+1 (from_right): row_shr:1 / row_shl:1
-// within rows of 16 lanes for P <= 16, wave_shr:1 / wave_shl:1 across the
-// wavefront for P = 32.  A lane without a source keeps `old`: the callers pass
-// the destination's own previous value, which is +inf on those lanes from the
-// start (so no register has to be set to +inf before every move).
+// Lane l gets lane l-1's v (from_left) or lane l+1's (from_right): row_shr:1 /
+// row_shl:1 within rows of 16 lanes when groups tile those rows (P = 4, 8,
+// 16), wave_shr:1 / wave_shl:1 across the wavefront otherwise (P = 12, 32).
+// The value received is raised to `pen`, the bits of +inf on the lanes at a
+// group edge (which must see +inf from outside the band) and 0 elsewhere: an
+// integer max on the bit patterns, exact for the values of the sweep (each
+// non-negative or +inf, whose patterns order as the values do).  A lane
+// without a source reads 0 and so gets `pen`.  The compiler folds the move
+// and the max into one v_max_i32 with the DPP shift on its first operand.
 template <int P>
-__device__ __forceinline__ float from_left(float old, float v) {
-    constexpr int ctrl = P <= 16 ? 0x111 : 0x138;
-    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v), ctrl, 0xF, 0xF, false));
+__device__ __forceinline__ float from_left(float v, int pen) {
+    constexpr int ctrl = 16 % P == 0 ? 0x111 : 0x138;
+    return __int_as_float(max(__builtin_amdgcn_update_dpp(0, __float_as_int(v), ctrl, 0xF, 0xF, true), pen));
 }
 template <int P>
-__device__ __forceinline__ float from_right(float old, float v) {
-    constexpr int ctrl = P <= 16 ? 0x101 : 0x130;
-    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v), ctrl, 0xF, 0xF, false));
+__device__ __forceinline__ float from_right(float v, int pen) {
+    constexpr int ctrl = 16 % P == 0 ? 0x101 : 0x130;
+    return __int_as_float(max(__builtin_amdgcn_update_dpp(0, __float_as_int(v), ctrl, 0xF, 0xF, true), pen));
 }
 
 // Lane constants of a split group.
 struct SplitLane {
     int p;          // lane within the group
-    bool first;     // p == 0 (no band cell to the left)
-    bool last;      // p == P-1 (no band cell to the right)
+    int pen_first;  // p == 0 (no band cell to the left): the bits of +inf, else 0
+    int pen_last;   // p == P-1 (no band cell to the right): the bits of +inf, else 0
     bool shrt;      // holds w-1 cells
 };
 
 // One step of one lane: row r of its cells.  MASK: commit only when `act`.
-// left_in and up_dpp persist across steps as the DPP destinations (+inf on
-// the lanes without a source; for P != 16 the group edges inside a row are
-// selected to +inf after each move).
+// left_in carries the left value of the first cell into the next step; both
+// it and up_dpp are +inf on the lanes at a group edge.
 template <int P, int w, bool MASK>
 __device__ __forceinline__ void split_step(float (&st)[w], float &left_in, float &up_dpp, const SplitLane &ln,
                                            float x, const float *yv, bool act) {
@@ -95,15 +98,13 @@ __device__ __forceinline__ void split_step(float (&st)[w], float &left_in, float
         nw[u] = v;
         if (u == 0) {
             // cell K_{p+1} of row r-1 from the lane to the right (its first cell of this step)
-            up_dpp = from_right<P>(up_dpp, v);
-            if constexpr (P != 16) up_dpp = ln.last ? kInf : up_dpp;
+            up_dpp = from_right<P>(v, ln.pen_last);
         }
     }
 #pragma unroll
     for (int u = 0; u < w; ++u) st[u] = nw[u];
     const float send = ln.shrt ? st[w - 2] : st[w - 1];  // the lane's last band cell
-    left_in = from_left<P>(left_in, send);
-    if constexpr (P != 16) left_in = ln.first ? kInf : left_in;
+    left_in = from_left<P>(send, ln.pen_first);
 }
 
 template <int P, int w, int U, bool MASK>
@@ -151,8 +152,8 @@ __global__ __launch_bounds__(64) void k_lane_split(const float *__restrict__ ws,
     const int grp = lane / P;
     SplitLane ln;
     ln.p = lane % P;
-    ln.first = ln.p == 0;
-    ln.last = ln.p == P - 1;
+    ln.pen_first = ln.p == 0 ? 0x7f800000 : 0;  // the bits of +inf
+    ln.pen_last = ln.p == P - 1 ? 0x7f800000 : 0;
     const bool valid = grp < it.cnt;
     int bl;
     int64_t slot;
@@ -222,17 +223,20 @@ constexpr std::array<SplitFn, sizeof...(I)> make_split_table(std::index_sequence
 constexpr int kSplitWidths = kSplitMaxW - kSplitMinW + 1;
 const std::array<SplitFn, kSplitWidths> kSplit4 = make_split_table<4>(std::make_index_sequence<kSplitWidths>{});
 const std::array<SplitFn, kSplitWidths> kSplit8 = make_split_table<8>(std::make_index_sequence<kSplitWidths>{});
-// W <= 127 needs w <= 8 for P = 16 and w <= 4 for P = 32
+// W <= 127 needs w <= 11 for P = 12, w <= 8 for P = 16 and w <= 4 for P = 32
+const std::array<SplitFn, 11 - kSplitMinW + 1> kSplit12 = make_split_table<12>(std::make_index_sequence<11 - kSplitMinW + 1>{});
 const std::array<SplitFn, 8 - kSplitMinW + 1> kSplit16 = make_split_table<16>(std::make_index_sequence<8 - kSplitMinW + 1>{});
 const std::array<SplitFn, 4 - kSplitMinW + 1> kSplit32 = make_split_table<32>(std::make_index_sequence<4 - kSplitMinW + 1>{});
 
 }  // namespace
 
+int split_max_cells(int P) { return P == 32 ? 4 : (P == 16 ? 8 : (P == 12 ? 11 : kSplitMaxW)); }
+
 bool lane_split_supported(int P, int W) {
     if (!lane_width_supported(W)) return false;
-    if (P != 4 && P != 8 && P != 16 && P != 32) return false;
+    if (P != 4 && P != 8 && P != 12 && P != 16 && P != 32) return false;
     const int w = (W + P - 1) / P;
-    return w >= kSplitMinW && w <= (P == 32 ? 4 : (P == 16 ? 8 : kSplitMaxW));
+    return w >= kSplitMinW && w <= split_max_cells(P);
 }
 
 hipError_t launch_lane_split(int P, int W, const float *ws, const SeriesInfo *ser, const DatasetInfo *dsi,
@@ -241,7 +245,11 @@ hipError_t launch_lane_split(int P, int W, const float *ws, const SeriesInfo *se
     if (!lane_split_supported(P, W)) return hipErrorInvalidValue;
     if (n_items == 0) return hipSuccess;
     const int i = (W + P - 1) / P - kSplitMinW;
-    const SplitFn f = P == 4 ? kSplit4[i] : (P == 8 ? kSplit8[i] : (P == 16 ? kSplit16[i] : kSplit32[i]));
+    const SplitFn f = P == 4    ? kSplit4[i]
+                      : P == 8  ? kSplit8[i]
+                      : P == 12 ? kSplit12[i]
+                      : P == 16 ? kSplit16[i]
+                                : kSplit32[i];
     return f(ws, ser, dsi, items, partners, n_items, W, stream);
 }
 

@@ -588,10 +588,10 @@ def test_pair_list_medoids_on_lane_kernel():
     plan.destroy()
     got = out.cpu().numpy()
     # 1,500 pairs are 25 tiles of 64: the planner spreads each pair over more
-    # lanes to fill the device -- 8 (8 pairs per wavefront), the most that
-    # leaves 3 of the 25 band cells to a lane
-    assert [g["pairs_per_wave"] for g in desc["lane_groups"]] == [8]
-    assert info["n_wave_items"] == 0 and info["n_lane_items"] >= len(pairs) // 8
+    # lanes to fill the device -- 12 (5 pairs per wavefront), the most that
+    # gives a lane 3 of the 25 band cells (ceil(25/12) = 3)
+    assert [g["pairs_per_wave"] for g in desc["lane_groups"]] == [5]
+    assert info["n_wave_items"] == 0 and info["n_lane_items"] >= len(pairs) // 5
     full = run(ds)
     self_pair = pairs[:, 0] == pairs[:, 1]
     assert np.all(got[self_pair] == 0.0)
@@ -605,9 +605,11 @@ def test_pair_list_medoids_on_lane_kernel():
 # ---------------------------------------------------------------- split lane-band kernel
 
 # (lanes per pair, windows): band widths 2w+1 with 3 to 4 (32 lanes), 8 (16
-# lanes) or 16 (8 and 4 lanes) cells per lane, with 1 to 31 short lanes
-SPLIT_CASES = [(32, [32, 40, 47, 48, 51, 63]), (16, [16, 20, 23, 24, 40, 51, 63]), (8, [8, 11, 12, 30, 51, 60, 63]),
-               (4, [4, 5, 13, 20, 31])]
+# lanes), 11 (12 lanes: 5 pairs per wavefront and 4 idle lanes, groups across
+# the rows of 16 lanes) or 16 (8 and 4 lanes) cells per lane, with 1 to 31
+# short lanes
+SPLIT_CASES = [(32, [32, 40, 47, 48, 51, 63]), (16, [16, 20, 23, 24, 40, 51, 63]),
+               (12, [12, 17, 18, 23, 24, 51, 60, 63]), (8, [8, 11, 12, 30, 51, 60, 63]), (4, [4, 5, 13, 20, 31])]
 
 
 @pytest.mark.parametrize("P,windows", SPLIT_CASES)
@@ -643,21 +645,23 @@ def test_split_lane_kernel_pair_lists_and_ranges():
     pairs = np.stack([rng.integers(0, ds.N, 700), rng.integers(0, ds.N, 700)], axis=1).astype(np.int32)
     series = B.device_series(ds)
     outs = {}
-    for ppw in (64, 8, 4, 2):  # band of 103 cells: 13, 7 or 4 per lane (16 pairs per wavefront would need 26)
+    # band of 103 cells: 13, 9, 7 or 4 per lane (16 pairs per wavefront would need 26)
+    for ppw in (64, 8, 5, 4, 2):
         out = torch.full((len(pairs),), float("nan"), device="cuda")
         B.dtw_pairs(series, ds.lengths, ds.offsets, ds.window, pairs, out, accum="plain", pairs_per_wave=ppw)
         torch.cuda.synchronize()
         outs[ppw] = out.cpu().numpy()
-    for ppw in (8, 4, 2):
+    for ppw in (8, 5, 4, 2):
         assert np.array_equal(outs[ppw], outs[64]), "pair list, %d pairs per wavefront" % ppw
     sel = rng.choice(len(pairs), 60, replace=False)
     assert_close(outs[4][sel], oracle_pairs(ds, pairs[sel, 0], pairs[sel, 1]), what="split pair list")
     # a condensed sub-range: rows of the matrix in runs of 64/P partners
     full = run(ds, accum="plain", pairs_per_wave=64)
     k0, k1 = 1234, 4321
-    part = run(ds, accum="plain", pairs_per_wave=8, k_range=(k0, k1))
-    assert np.array_equal(part[k0:k1], full[k0:k1])
-    assert np.all(np.isnan(part[:k0])) and np.all(np.isnan(part[k1:]))
+    for ppw in (8, 5):
+        part = run(ds, accum="plain", pairs_per_wave=ppw, k_range=(k0, k1))
+        assert np.array_equal(part[k0:k1], full[k0:k1]), "%d pairs per wavefront" % ppw
+        assert np.all(np.isnan(part[:k0])) and np.all(np.isnan(part[k1:]))
 
 
 def test_split_lane_kernel_rejections():
