@@ -123,7 +123,7 @@ __global__ __launch_bounds__(kRowBlock) void k_row_cluster_sums(const float *__r
 }
 
 // Each entry of D once: workgroup (SC, SR) of kSilR wavefronts covers rows
-// [256 SR, 256 SR + 256) (wavefront w: row block I = 4 SR + w, 64 rows) and
+// [512 SR, 512 SR + 512) (wavefront w: row block I = 8 SR + w, 64 rows) and
 // columns [512 SC, 512 SC + 512) (kSilT column tiles); a tile (I, J) is
 // processed only for J >= I, and on the diagonal (J == I) only for i < j, so
 // every condensed entry D(i, j), i < j, is read by exactly one wavefront.  It
@@ -132,7 +132,7 @@ __global__ __launch_bounds__(kRowBlock) void k_row_cluster_sums(const float *__r
 //  * lane = column j: the tile is loaded row by row (coalesced: 64
 //    consecutive entries of row i of the condensed triangle) into registers,
 //    and each lane adds its column's values over the tile's rows (label of
-//    the row wave-uniform); the four wavefronts' column sums of the tile are
+//    the row wave-uniform); the eight wavefronts' column sums of the tile are
 //    then added in wavefront order through LDS and written to
 //    Pcol[SR][J][j] (per super-row SR);
 //  * lane = row i: the tile goes through LDS to be read transposed, and each
@@ -142,21 +142,40 @@ __global__ __launch_bounds__(kRowBlock) void k_row_cluster_sums(const float *__r
 // of consecutive series as one coalesced run.)
 // The per-series sums then add the Prow and Pcol partials in a fixed order,
 // so D is read once from HBM and the results repeat bit for bit.  K <= 16.
-constexpr int kSilR = 4;   // row blocks (wavefronts) per workgroup
-constexpr int kSilT = 8;   // column tiles per workgroup
+constexpr int kSilR = 8;  // row blocks (wavefronts) per workgroup
+constexpr int kSilT = 8;  // column tiles per workgroup
 constexpr int kSilRows = kSilR * kRowBlock, kSilCols = kSilT * kRowBlock;
-// the super-tiles (SR, SC) holding a tile on or above the diagonal
-__host__ __device__ constexpr bool sil_launched(int SR, int SC) { return kSilCols * SC + kSilCols - 1 >= kSilRows * SR; }
+// the super-tiles (SR, SC) holding a tile on or above the diagonal: SC >= sil_first_sc(SR)
 __host__ __device__ constexpr int sil_first_sc(int SR) { return kSilRows * SR / kSilCols; }
 __host__ __device__ constexpr int sil_last_sr(int SC) { return (kSilCols * SC + kSilCols - 1) / kSilRows; }
+// Super-tiles of an n_sr x n_sc grid on or above the diagonal
+__host__ __device__ inline int sil_count(int n_sr, int n_sc) {
+    int n = 0;
+    for (int SR = 0; SR < n_sr; ++SR) n += max(0, n_sc - sil_first_sc(SR));
+    return n;
+}
 
+//
+// One workgroup per super-tile on or above the diagonal, numbered row by row;
+// workgroup b takes super-tile (b mod 8) * ceil(n/8) + b / 8, so that the
+// hardware's round-robin over the 8 XCDs gives each XCD a run of neighbouring
+// super-tiles, which share the cache lines at their column boundaries in that
+// XCD's L2.
 __global__ __launch_bounds__(64 * kSilR) void k_cluster_sums_once(const float *__restrict__ D, int N,
                                                                   const int *__restrict__ labels, int K,
                                                                   double *__restrict__ Prow,
-                                                                  double *__restrict__ Pcol) {
+                                                                  double *__restrict__ Pcol, int n_sr, int n_sc,
+                                                                  int n_st) {
     __shared__ float tile[kSilR][kRowBlock][kRowBlock + 1];  // a wavefront's tile; reused for its column sums
-    const int SC = blockIdx.x, SR = blockIdx.y;
-    if (!sil_launched(SR, SC)) return;  // below the diagonal: no tile with J >= I (uniform per workgroup)
+    int t = (blockIdx.x % 8) * ((n_st + 7) / 8) + blockIdx.x / 8;
+    if (t >= n_st) return;  // uniform per workgroup
+    int SR = 0;
+    for (; SR < n_sr - 1; ++SR) {  // the super-row holding super-tile t (uniform)
+        const int cnt = n_sc - sil_first_sc(SR);
+        if (t < cnt) break;
+        t -= cnt;
+    }
+    const int SC = sil_first_sc(SR) + t;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;  // w: wave-uniform
     const int I = kSilR * SR + w, i0 = I * kRowBlock;
     Acc16 accr[1] = {Acc16{}};
@@ -393,11 +412,14 @@ int dtw_silhouette(const float *D, int32_t N, const int32_t *labels, int32_t K, 
     e = hipMemcpyAsync(d_sizes, sizes.data(), K * sizeof(int32_t), hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return hip_err(e, "hipMemcpy (cluster sizes)");
     static_assert(kSilhouetteMaxK <= 64, "four vectors of 16 accumulators");
-    if (once)
-        hipLaunchKernelGGL(k_cluster_sums_once, dim3(n_sc, n_sr), dim3(64 * kSilR), 0, s, D, N, labels, K, d_P, d_Pc);
-    else
+    if (once) {
+        const int n_st = sil_count(n_sr, n_sc);
+        hipLaunchKernelGGL(k_cluster_sums_once, dim3(8 * ((n_st + 7) / 8)), dim3(64 * kSilR), 0, s, D, N, labels, K,
+                           d_P, d_Pc, n_sr, n_sc, n_st);
+    } else {
         hipLaunchKernelGGL((k_row_cluster_sums<4, 16>), dim3(row_blocks, splits), dim3(kRowBlock), 0, s, D, N, labels,
                            K, tiles_per_split, d_P);
+    }
     if ((e = hipGetLastError()) != hipSuccess) return hip_err(e, "row-sum kernel launch");
     hipLaunchKernelGGL(k_silhouette_rows, dim3(red_blocks), dim3(kReduce), 0, s, d_P, splits, N, K, labels, d_sizes,
                        s_out, d_part, d_Pc, n_sr);
