@@ -38,15 +38,25 @@ namespace {
 // hoisting the loads of a whole row (which would exceed the SGPR file).
 // A chunk whose columns all lie outside [0, L) is skipped with a wave-uniform
 // branch: cells left of column 0 are +inf and stay +inf, and cells right of
-// column L-1 are never read by an admissible cell.
+// column L-1 are never read by an admissible cell.  For bands of up to
+// kLaneEdgeMaxW cells, row groups whose band reaches past column 0 or L-1 (the
+// first and last ~B rows) sweep in chunks of kLaneEdgeChunk steps, so that
+// fewer cells outside the matrix share a chunk with cells inside it (at
+// W = 51, L = 256: 0.8% more cells than the admissible ones instead of 2.5%);
+// the others in chunks of kLaneChunk.
 #ifndef DTWMI_LANE_ROWS
 #define DTWMI_LANE_ROWS 4
 #endif
 #ifndef DTWMI_LANE_CHUNK
 #define DTWMI_LANE_CHUNK 16
 #endif
+#ifndef DTWMI_LANE_EDGE_CHUNK
+#define DTWMI_LANE_EDGE_CHUNK 4
+#endif
 constexpr int kLaneRows = DTWMI_LANE_ROWS;
 constexpr int kLaneChunk = DTWMI_LANE_CHUNK;
+constexpr int kLaneEdgeChunk = DTWMI_LANE_EDGE_CHUNK;
+constexpr int kLaneEdgeMaxW = 63;
 
 template <int W>
 __device__ __forceinline__ void lane_cell(float (&st)[W], int k, float xi, float yk) {
@@ -102,6 +112,42 @@ __device__ __forceinline__ void lane_group(float (&st)[W], const float (&x)[R], 
 // lanes and the base needs no conversion.
 constexpr int kLaneRebaseRows = 32;
 
+// Row groups i .. iend-1 (iend - i a multiple of R) in chunks of C steps; the
+// y window and x of the first group are read here, those of the following
+// groups one group ahead.
+template <int W, int R, int C, bool RB>
+__device__ __forceinline__ void lane_rows(float (&st)[W], float &base, const float *__restrict__ ycol,
+                                          const float *__restrict__ xrow, int &i, int iend, int B, int L) {
+    if (i >= iend) return;
+    float ycur[C + R - 1];
+#pragma unroll
+    for (int u = 0; u < C + R - 1; ++u) ycur[u] = ycol[i + u - (R - 1)];
+    float x[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) x[r] = xrow[i + r];
+    for (; i < iend; i += R) {
+        float xn[R];  // next group's x, requested one group ahead (stays inside the pad)
+#pragma unroll
+        for (int r = 0; r < R; ++r) xn[r] = xrow[i + R + r];
+        lane_group<W, R, C, 0>(st, x, ycol + i - (R - 1), ycol + i + 1, ycur, i - B, L);
+#pragma unroll
+        for (int r = 0; r < R; ++r) x[r] = xn[r];
+        if constexpr (RB) {
+            static_assert(kLaneRebaseRows % R == 0, "renormalise between row groups");
+            if ((i + R) % kLaneRebaseRows == 0) {  // every row of the group is complete here
+                float mn = st[0];
+#pragma unroll
+                for (int k = 1; k < W; ++k) mn = fminf(mn, st[k]);
+                const float nb = base + (mn < kInf ? mn : 0.0f);
+                const float d = nb - base;
+#pragma unroll
+                for (int k = 0; k < W; ++k) st[k] -= d;
+                base = nb;
+            }
+        }
+    }
+}
+
 // Lane-band items have equal cost, so the kernel takes one item per workgroup
 // (hardware dispatch); an item loop would only add registers to this kernel.
 // Workgroups go to the 8 XCDs of the device in turn, so workgroup w takes item
@@ -146,32 +192,23 @@ __global__ __launch_bounds__(64) void k_lane(const float *__restrict__ ws, const
     float base = 0.0f;  // rebased form only
     int i = 0;
     if (L >= R) {
-        float ycur[C + R - 1];
-#pragma unroll
-        for (int u = 0; u < C + R - 1; ++u) ycur[u] = ycol[u - (R - 1)];
-        float x[R];
-#pragma unroll
-        for (int r = 0; r < R; ++r) x[r] = xrow[r];
-        for (; i + R <= L; i += R) {
-            float xn[R];  // next group's x, requested one group ahead (stays inside the pad)
-#pragma unroll
-            for (int r = 0; r < R; ++r) xn[r] = xrow[i + R + r];
-            lane_group<W, R, C, 0>(st, x, ycol + i - (R - 1), ycol + i + 1, ycur, i - B, L);
-#pragma unroll
-            for (int r = 0; r < R; ++r) x[r] = xn[r];
-            if constexpr (RB) {
-                static_assert(kLaneRebaseRows % R == 0, "renormalise between row groups");
-                if ((i + R) % kLaneRebaseRows == 0) {  // every row of the group is complete here
-                    float mn = st[0];
-#pragma unroll
-                    for (int k = 1; k < W; ++k) mn = fminf(mn, st[k]);
-                    const float nb = base + (mn < kInf ? mn : 0.0f);
-                    const float d = nb - base;
-#pragma unroll
-                    for (int k = 0; k < W; ++k) st[k] -= d;
-                    base = nb;
-                }
-            }
+        // A group starting at row i sweeps columns i-B (its first row's cell
+        // 0) to i+R-1+B (its last row's cell W-1): groups at i < itop reach
+        // left of column 0, groups at i >= ibot right of column L-1; both
+        // sweep in chunks of kLaneEdgeChunk steps for bands up to
+        // kLaneEdgeMaxW cells (wider bands hold fewer wavefronts per SIMD,
+        // which then wait longer for the y values of the more numerous
+        // chunks than the skipped cells save).
+        constexpr int CE = (W <= kLaneEdgeMaxW && kLaneEdgeChunk < C) ? kLaneEdgeChunk : C;
+        const int Lr = L - L % R;
+        if constexpr (CE == C) {
+            lane_rows<W, R, C, RB>(st, base, ycol, xrow, i, Lr, B, L);
+        } else {
+            const int itop = min(Lr, R * ((B + R - 1) / R));
+            const int ibot = max(itop, min(Lr, R * ((L - B - R + 1 + R - 1) / R)));
+            lane_rows<W, R, CE, RB>(st, base, ycol, xrow, i, itop, B, L);
+            lane_rows<W, R, C, RB>(st, base, ycol, xrow, i, ibot, B, L);
+            lane_rows<W, R, CE, RB>(st, base, ycol, xrow, i, Lr, B, L);
         }
     }
     if constexpr (R > 1) {
