@@ -12,8 +12,11 @@ FP64 CPU oracle timed on a bounded sample of the same workload.  The default
 run (8000 series of 256 points, window 25, the largest single-matrix
 workload) adds, under "extra": the equal-length banded matrix (1000 x 512,
 window 51) as the equal-size rate, the 64-dataset batched plan replayed from a
-HIP graph with its ratio to that rate, and the 500 x 4096 long-series matrix
-under the default accumulation with its error against the oracle.
+HIP graph with its ratio to that rate (and the same plan autotuned), the
+k-medoids pair list on the 1000 x 512 data, the 500 x 4096 long-series matrix
+under the default accumulation with its error against the oracle, and the
+headline matrix with its series stored as BF16 and as FP16, each with its
+error against the oracle on the stored values.
 """
 from __future__ import annotations
 
@@ -341,6 +344,23 @@ def extra_workloads(dev, stream, steps):
     c3.update(accum="auto (FP64 sums on these unwindowed 8,191-cell paths)", pairs_checked=len(pi),
               max_rel_err=float(rel.max()), mean_rel_err=float(rel.mean()), description=WORKLOADS["c3"])
     out["c3_500x4096_default_accumulation"] = c3
+    # the headline matrix with its series stored as BF16 / FP16 (widened to
+    # FP32 once by the staging kernel; error against the oracle on the stored
+    # values, whose bound is 1e-3 for these forms)
+    ds5 = synth.config5()
+    rng = np.random.default_rng(8000)
+    a5, b5 = rng.integers(0, ds5.N, size=(2, 6000))
+    keep = a5 != b5
+    pi5, pj5 = np.minimum(a5, b5)[keep].astype(np.int32), np.maximum(a5, b5)[keep].astype(np.int32)
+    k5 = pi5.astype(np.int64) * ds5.N - pi5.astype(np.int64) * (pi5 + 1) // 2 + (pj5 - pi5 - 1)
+    for dt in ("bf16", "f16"):
+        dsd = synth.with_dtype(ds5, dt)
+        r5, o5 = rate([dsd], False, 20)
+        ref, _ = oracle.dtw_pairs(synth.stored_as_f64(dsd), dsd.offsets, dsd.lengths, pi5, pj5, dsd.window)
+        rel = np.abs(o5[0][k5].astype(np.float64) - ref) / np.maximum(ref, 1e-300)
+        r5.update(storage=dt, pairs_checked=int(len(pi5)), max_rel_err=float(rel.max()),
+                  mean_rel_err=float(rel.mean()), description=WORKLOADS["c5"] + ", series stored as " + dt)
+        out["c5_8000x256_w25_%s_storage" % dt] = r5
     return out
 
 
@@ -373,7 +393,8 @@ def main(argv=None):
     ap.add_argument("--describe", metavar="FILE", default="",
                     help="write the plan's kernel groups (dtw_plan_describe JSON) to FILE")
     ap.add_argument("--no-extra", action="store_true",
-                    help="skip the extra workloads of the default run (equal-size, batched graph, long series)")
+                    help="skip the extra workloads of the default run (equal-size, k-medoids list, batched graph, "
+                         "long series, BF16/FP16 storage)")
     ap.add_argument("--graph", action="store_true",
                     help="time replays of a HIP graph captured from one execute instead of eager executes")
     ap.add_argument("--copy-calibration-mb", type=float, default=0.0,
