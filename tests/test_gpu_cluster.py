@@ -31,7 +31,7 @@ def _labels(seed, N, K, empty=()):
     return lab
 
 
-# N across the 256-row and 512-column blocks of the single-read kernel (K <= 16)
+# N across the 512-row and 512-column super-tiles of the single-read kernel (K <= 16)
 # and K past it (17, 64: the two-read kernel)
 @pytest.mark.parametrize("N,K", [(2, 2), (3, 2), (65, 3), (130, 7), (255, 16), (257, 5), (513, 16), (1025, 12),
                                  (2100, 9), (300, 17), (300, 64), (1000, 10)])
