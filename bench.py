@@ -59,7 +59,8 @@ MODE_OPS = {"plain": (3, PEAK_LANE_OPS_T, "TOP/s (FP32 VALU lane-ops)"),
 PROFILE_LABELS = {("c2", "auto", "auto", "f32"): "lane_band_W103_c2",
                   ("c5", "auto", "auto", "f32"): "lane_band_W51_c5",
                   ("c3", "auto", "auto", "f32"): "strip_f64_H16x4_c3",
-                  ("c4", "auto", "auto", "f32"): "batched_c4"}
+                  ("c4", "auto", "auto", "f32"): "batched_c4",
+                  ("c2m", "auto", "auto", "f32"): "lane_split_P12_c2m"}
 
 WORKLOADS = {
     "c2": "equal-length banded matrix: 1000 random walks x 512, window 51",
@@ -504,7 +505,10 @@ def main(argv=None):
             "kernel_ms": round(k_avg, 4),
             "ops_per_cell": ops_cell,
             "ops_per_launch": ops_cell * cells,
-            "traffic": recorded_traffic(PROFILE_LABELS.get((args.workload, args.kernel, args.accum, args.dtype), "-")),
+            # the profiles were taken with the automatic plan: no traffic for forced shapes or dispatch
+            "traffic": recorded_traffic(PROFILE_LABELS.get((args.workload, args.kernel, args.accum, args.dtype), "-"))
+            if (args.pairs_per_wave == 0 and args.rows_per_lane == 0 and args.dispatch == "queue"
+                and not args.autotune) else None,
         },
         "wall_s": round(wall, 3),
     }
