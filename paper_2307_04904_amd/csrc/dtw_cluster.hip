@@ -155,7 +155,6 @@ __host__ __device__ inline int sil_count(int n_sr, int n_sc) {
     return n;
 }
 
-//
 // One workgroup per super-tile on or above the diagonal, numbered row by row;
 // workgroup b takes super-tile (b mod 8) * ceil(n/8) + b / 8, so that the
 // hardware's round-robin over the 8 XCDs gives each XCD a run of neighbouring
