@@ -80,10 +80,10 @@ def medoid_pairs(N, k, seed=230704906):
     return np.array([[i, m] for m in med for i in range(N)], dtype=np.int32)
 
 
-def make_datasets(name, dtype="f32"):
+def make_datasets(name, dtype="f32", c4_seed=None):
     from paper_2307_04904_amd import synth
     if name == "c4":
-        return synth.config4()
+        return synth.config4(seed=c4_seed)
     if name == "c3":
         return [synth.config3(dtype=dtype)]
     return [{"c1": synth.config1, "c2": synth.config2, "c2m": synth.config2, "c3": synth.config3,
@@ -396,6 +396,9 @@ def main(argv=None):
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the extra workloads of the default run (equal-size, k-medoids list, batched graph, "
                          "long series, BF16/FP16 storage)")
+    ap.add_argument("--c4-seed", type=int, default=None,
+                    help="with --workload c4: another instance of the batched recipe (a workload the cost model "
+                         "was not calibrated on)")
     ap.add_argument("--graph", action="store_true",
                     help="time replays of a HIP graph captured from one execute instead of eager executes")
     ap.add_argument("--copy-calibration-mb", type=float, default=0.0,
@@ -420,7 +423,7 @@ def main(argv=None):
         print(json.dumps({"copy_calibration_bytes_per_copy": 4 * n, "copies": 5}), flush=True)
         return 0
 
-    dsets = make_datasets(args.workload, args.dtype)
+    dsets = make_datasets(args.workload, args.dtype, args.c4_seed)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     series = [binding.device_series(ds, dev) for ds in dsets]
@@ -481,7 +484,8 @@ def main(argv=None):
         "data": "synthetic",
         "timing": "hip graph replays" if args.graph else "eager executes",
         "config": {"workload": (dsets[0].name + ("_medoids%d" % MEDOIDS if pair_list is not None else "")
-                                if len(dsets) == 1 else args.workload + "_batched_64_datasets"),
+                                if len(dsets) == 1 else args.workload + "_batched_64_datasets"
+                                + ("" if args.c4_seed is None else "_seed%d" % args.c4_seed)),
                    "description": WORKLOADS[args.workload], "datasets": len(dsets),
                    "N": [ds.N for ds in dsets] if len(dsets) > 1 else dsets[0].N,
                    "length": int(max(ds.lengths.max() for ds in dsets)),
@@ -508,7 +512,7 @@ def main(argv=None):
             # the profiles were taken with the automatic plan: no traffic for forced shapes or dispatch
             "traffic": recorded_traffic(PROFILE_LABELS.get((args.workload, args.kernel, args.accum, args.dtype), "-"))
             if (args.pairs_per_wave == 0 and args.rows_per_lane == 0 and args.dispatch == "queue"
-                and not args.autotune) else None,
+                and not args.autotune and args.c4_seed is None) else None,
         },
         "wall_s": round(wall, 3),
     }

@@ -158,13 +158,15 @@ def config3(dtype: str = "f32", N: int = 500, L: int = 4096) -> Dataset:
 WINDOW_FRACTIONS = (0.0, 0.05, 0.10, 0.20, None)  # None = no window
 
 
-def config4(n_datasets: int = 64, n_lo: int = 10, n_hi: int = 400, len_lo: int = 64, len_hi: int = 2048):
+def config4(n_datasets: int = 64, n_lo: int = 10, n_hi: int = 400, len_lo: int = 64, len_hi: int = 2048,
+            seed=None):
     """64 independent datasets of uneven size and uneven series lengths.
 
     N ~ U{n_lo..n_hi}; every series length ~ U{len_lo..len_hi}; window fraction
     p ~ U{0, 5%, 10%, 20%, none}, turned into w = floor(p * longest length).
+    `seed` (default: the workload's own) draws another instance of the recipe.
     """
-    children = np.random.SeedSequence(SEEDS["c4"]).spawn(n_datasets)
+    children = np.random.SeedSequence(SEEDS["c4"] if seed is None else seed).spawn(n_datasets)
     out = []
     for d, child in enumerate(children):
         rng = _rng(child)
