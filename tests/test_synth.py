@@ -31,6 +31,12 @@ def test_config4_ranges():
         assert 10 <= d.N <= 400
         assert d.lengths.min() >= 64 and d.lengths.max() <= 2048
         assert d.window == -1 or d.window == int(np.floor(d.meta["window_fraction"] * d.lengths.max()))
+    # the default seed is the workload's own; another seed draws another instance of the recipe
+    same = synth.config4(n_datasets=6, seed=synth.SEEDS["c4"])
+    assert all(np.array_equal(a.values, b.values) and a.window == b.window for a, b in zip(ds, same))
+    other = synth.config4(n_datasets=6, seed=1)
+    assert [d.N for d in other] != [d.N for d in ds]
+    assert all(10 <= d.N <= 400 and 64 <= d.lengths.min() and d.lengths.max() <= 2048 for d in other)
 
 
 def test_bf16_and_f16_are_rne_casts():
