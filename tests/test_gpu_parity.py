@@ -602,6 +602,27 @@ def test_pair_list_medoids_on_lane_kernel():
     assert_close(got[sel], oracle_pairs(ds, pairs[sel, 0], pairs[sel, 1]), what="medoid pairs")
 
 
+# ---------------------------------------------------------------- lane-band kernel: band-edge row groups
+
+@pytest.mark.parametrize("w", [5, 12, 25, 31, 32])
+def test_lane_kernel_edge_row_groups(w):
+    # bands of up to 63 cells sweep the row groups that reach past column 0
+    # or L-1 in short chunks and the others in long ones; lengths around the
+    # band, twice the band and the row-group size put the switch between the
+    # two at every offset.  Against the split kernel (its own sweep) bit for
+    # bit, and against the oracle
+    _gpu()
+    W = 2 * w + 1
+    ppw = 16 if W < 24 else 8  # 4 or 8 lanes per pair: at least 3 band cells a lane
+    for L in sorted({w + 1, w + 2, w + 5, 2 * w, 2 * w + 3, 2 * w + 6, 3 * w + 1, 4 * w + 7}):
+        ds = synth.small_random(seed=8100 + 13 * w + L, N=9, len_lo=L, len_hi=L, window=w)
+        lane = run(ds, kernel="lane", accum="plain", pairs_per_wave=64)
+        split = run(ds, kernel="lane", accum="plain", pairs_per_wave=ppw)
+        assert np.array_equal(lane, split), "w=%d L=%d: lane and split kernels differ" % (w, L)
+        pi, pj = oracle.all_pairs_list(ds.N)
+        assert_close(lane, oracle_pairs(ds, pi, pj), what="lane w=%d L=%d" % (w, L))
+
+
 # ---------------------------------------------------------------- split lane-band kernel
 
 # (lanes per pair, windows): band widths 2w+1 with 3 to 4 (32 lanes), 8 (16
